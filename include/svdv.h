@@ -1,0 +1,167 @@
+/*
+ * svdv -- singular values of dense matrices on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the two-stage QR-based singular-value algorithm whose stage-1
+ * kernels the paper auto-tunes (evaluation section, "Algorithm", Algorithm 1
+ * and Algorithm 2):
+ *   stage 1  dense -> upper band of bandwidth TS (the tile size): for each
+ *            diagonal tile k, a QR sweep on the tile column and an LQ sweep on
+ *            the tile row, each a panel factorisation followed by a trailing
+ *            update that applies the panel's orthogonal factor;
+ *   stage 2  band -> upper bidiagonal (bulge chasing);
+ *   stage 3  bidiagonal -> singular values.
+ * Every transform is orthogonal, so the singular values are those of A.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major with a leading dimension (lda >= max(1, rows)).
+ *   A row-major (m, n) array is the column-major (n, m) matrix A^T, which has
+ *   the same singular values: pass it as (n, m, lda = n).
+ * - Every matrix / vector pointer is a DEVICE pointer unless stated otherwise.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls only
+ *   enqueue work and never synchronise the host; a return of SVDV_OK means
+ *   "enqueued", results are valid once the caller synchronises the stream.
+ *   Faults inside kernels surface as HIP errors at that synchronisation.
+ * - The caller owns A and S.  A is never written.  The library owns a
+ *   workspace per (device, stream), grown on demand with hipMalloc (the first
+ *   call at a new size allocates) and released by svdv_release().  Calls that
+ *   overlap on the same stream are ordered by the stream; calls on different
+ *   streams use different workspaces.
+ * - Errors are negative svdv_status values; the library never aborts and
+ *   never throws across this interface.  svdv_last_error() gives detail.
+ */
+#ifndef SVDV_H
+#define SVDV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SVDV_F32 = 0, SVDV_F64 = 1 } svdv_dtype;
+
+typedef enum {
+  SVDV_OK = 0,
+  SVDV_ERR_INVALID_ARG = -1, /* negative size, lda too small, NULL pointer with nonzero size, bad dtype */
+  SVDV_ERR_UNSUPPORTED = -2, /* configuration outside the compiled set or beyond LDS / thread limits */
+  SVDV_ERR_NO_MEMORY = -3,   /* workspace allocation failed */
+  SVDV_ERR_HIP = -4          /* a HIP runtime call failed (launch, event, graph) */
+} svdv_status;
+
+/*
+ * Tunable configuration (the auto-tuner's search space; Eq. 1 of the paper
+ * picks the argmin over these).
+ *   tile         TS = bandwidth of stage 1, in {16, 32, 64, 128}.  It fixes the
+ *                number of panel steps (2 * ceil(n / TS)): the paper's only
+ *                pipeline parameter.
+ *   threads      workgroup size of the stage-1 trailing-update kernel,
+ *                {64, 128, 256, 512, 1024}; each wave owns its own column tiles.
+ *   inner_block  16-column MFMA tiles held per wave in the trailing update,
+ *                {1, 2, 4, 8} (register blocking).
+ *   sweep_width  bulge-chasing sweeps advanced together by one workgroup in
+ *                stage 2, {1, ..., 8}.
+ *   update_precision  0 = trailing updates in the input precision;
+ *                2 = BF16 MFMA operands, 3 = FP16 MFMA operands (float32 input
+ *                only; accumulation stays float32, panels, stage 2 and stage 3
+ *                are unaffected).
+ */
+typedef struct {
+  int32_t tile;
+  int32_t threads;
+  int32_t inner_block;
+  int32_t sweep_width;
+  int32_t update_precision;
+} svdv_config;
+
+/*
+ * Singular values of the m x n matrix A (dtype SVDV_F32 or SVDV_F64), written
+ * to S[0 .. min(m,n)-1] in A's dtype, descending and non-negative.
+ * m == 0 or n == 0: returns SVDV_OK and writes nothing.
+ * Non-finite input propagates NaN into S (no check on this path).
+ * The tuned default configuration for (m, n, dtype) is used.
+ */
+int svd_values(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream);
+
+/* As svd_values with an explicit configuration (cfg == NULL: tuned default).
+ * SVDV_ERR_UNSUPPORTED marks a configuration the auto-tuner must skip. */
+int svd_values_ex(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream,
+                  const svdv_config* cfg);
+
+/*
+ * Batched singular values of `batch` independent matrices of uneven sizes.
+ *   A_array   HOST array [batch] of device pointers to column-major matrices.
+ *   m, n, lda HOST arrays [batch].
+ *   S         device buffer; matrix i writes min(m[i], n[i]) values at
+ *             S + S_offset[i] elements (S_offset: HOST array [batch]).
+ *   cfg       NULL: per-size tuned defaults; otherwise one config for all.
+ * The whole batch is one stream-ordered sequence of persistent launches over
+ * all matrices at once, captured in a hipGraph and replayed on later calls
+ * with the same shapes.
+ */
+int svd_values_batched(const void* const* A_array, const int64_t* m, const int64_t* n, const int64_t* lda,
+                       int64_t batch, int32_t dtype, void* S, const int64_t* S_offset, void* stream,
+                       const svdv_config* cfg);
+
+/* The configuration svd_values would use for (m, n, dtype) (HOST out-pointer). */
+int svdv_default_config(int64_t m, int64_t n, int32_t dtype, svdv_config* out);
+
+/* SVDV_OK if cfg is runnable for (m, n, dtype), else SVDV_ERR_UNSUPPORTED / SVDV_ERR_INVALID_ARG.
+ * Needs no GPU (pure host validation). */
+int svdv_check_config(int64_t m, int64_t n, int32_t dtype, const svdv_config* cfg);
+
+/*
+ * Per-stage entry points.  They run the same kernels as svd_values (not a
+ * second code path) and exist so each stage can be checked on its own.
+ *
+ * svdv_stage_band: stage 1 (Algorithm 1).  Writes the n' x n' band
+ *   (n' = min(m, n)) as float64 into `band`, row i at band + i * ldband,
+ *   band[i * ldband + d] = B(i, i + d) for d = 0 .. TS (entries past column
+ *   n'-1 are zero).  ldband >= TS + 1.  Values are unscaled (the internal
+ *   power-of-two scaling is undone exactly).
+ */
+int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, double* band, int64_t ldband,
+                    void* stream, const svdv_config* cfg);
+
+/*
+ * svdv_stage_bidiag: stage 2.  Input: an n x n upper band of bandwidth b in the
+ * layout written by svdv_stage_band (float64).  Output: the upper bidiagonal,
+ * d[0..n-1] (diagonal) and e[0..n-2] (superdiagonal), float64.  Signs of d, e
+ * are not normalised.  cfg->sweep_width selects the schedule; the result is
+ * bitwise identical for every sweep_width.  b must be one of the tile sizes.
+ */
+int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, double* d, double* e, void* stream,
+                      const svdv_config* cfg);
+
+/*
+ * svdv_stage_values: stage 3.  Singular values of the upper bidiagonal (d, e)
+ * (float64, n and n-1 entries), written descending to S in out_dtype.
+ */
+int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_dtype, void* S, void* stream);
+
+/*
+ * svdv_apply_qt: the stage-1 trailing-update kernel on its own (Algorithm 2's
+ * operation, in compact-WY form): C <- (I - V T V^T)^T C for side = 0, or
+ * C <- C (I - V T V^T) for side = 1.
+ *   V  h x k (side 0) or w x k (side 1), column-major, leading dimension ldv,
+ *      unit lower trapezoidal as stored (entries above the diagonal must be 0,
+ *      the diagonal must be 1: they are read as given).
+ *   T  k x k upper triangular, column-major, leading dimension ldt.
+ *   C  h x w, column-major, leading dimension ldc, updated in place.
+ *   k  <= cfg->tile.  All three in `dtype`.
+ */
+int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* C, int64_t ldc, int64_t h, int64_t w,
+                  int64_t k, int32_t dtype, int32_t side, void* stream, const svdv_config* cfg);
+
+/* Text for a status code (static string). */
+const char* svdv_status_string(int status);
+/* Detail of the last error on the calling thread (thread-local, static lifetime). */
+const char* svdv_last_error(void);
+/* Free every cached workspace and graph (synchronises the devices that own them). */
+int svdv_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVDV_H */

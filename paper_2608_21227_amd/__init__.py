@@ -1,0 +1,257 @@
+"""svdv: singular values of dense matrices on an AMD Instinct MI355X.
+
+Thin ctypes binding over the C-ABI library ``libsvdv.so`` (declared in
+``include/svdv.h``).  This module only marshals arguments: every step of the
+computation runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream.  If the library has not been built the functions raise
+``RuntimeError`` -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import asdict, dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvdv.so")
+
+SVDV_F32, SVDV_F64 = 0, 1
+STATUS = {0: "SVDV_OK", -1: "SVDV_ERR_INVALID_ARG", -2: "SVDV_ERR_UNSUPPORTED", -3: "SVDV_ERR_NO_MEMORY",
+          -4: "SVDV_ERR_HIP"}
+
+# Every symbol include/svdv.h declares (checked by the CPU test-suite).
+EXPORTS = ["svd_values", "svd_values_ex", "svd_values_batched", "svdv_default_config", "svdv_check_config",
+           "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
+           "svdv_last_error", "svdv_release"]
+
+
+class SvdvError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class Unsupported(SvdvError):
+    """The configuration is outside the compiled set (the auto-tuner skips it)."""
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("threads", ctypes.c_int32), ("inner_block", ctypes.c_int32),
+                ("sweep_width", ctypes.c_int32), ("update_precision", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class Config:
+    tile: int = 32
+    threads: int = 256
+    inner_block: int = 2
+    sweep_width: int = 4
+    update_precision: int = 0
+
+    def _c(self) -> _Config:
+        return _Config(self.tile, self.threads, self.inner_block, self.sweep_width, self.update_precision)
+
+    def as_dict(self):
+        return asdict(self)
+
+
+_lib = None
+
+
+def lib():
+    """Load libsvdv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_21227_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        cfgp = ctypes.POINTER(_Config)
+        sig = {
+            "svd_values": [vp, i64, i64, i64, i32, vp, vp],
+            "svd_values_ex": [vp, i64, i64, i64, i32, vp, vp, cfgp],
+            "svd_values_batched": [vp, vp, vp, vp, i64, i32, vp, vp, vp, cfgp],
+            "svdv_default_config": [i64, i64, i32, cfgp],
+            "svdv_check_config": [i64, i64, i32, cfgp],
+            "svdv_stage_band": [vp, i64, i64, i64, i32, vp, i64, vp, cfgp],
+            "svdv_stage_bidiag": [vp, i64, i64, i64, vp, vp, vp, cfgp],
+            "svdv_stage_values": [vp, vp, i64, i32, vp, vp],
+            "svdv_apply_qt": [vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp, cfgp],
+            "svdv_release": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.svdv_status_string.argtypes = [ctypes.c_int]
+        L.svdv_status_string.restype = ctypes.c_char_p
+        L.svdv_last_error.argtypes = []
+        L.svdv_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        detail = lib().svdv_last_error().decode(errors="replace")
+        if rc == -2:
+            raise Unsupported(rc, detail)
+        raise SvdvError(rc, detail)
+
+
+def _cfg_ptr(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, dict):
+        cfg = Config(**cfg)
+    return ctypes.byref(cfg._c())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return SVDV_F32
+    if t.dtype == torch.float64:
+        return SVDV_F64
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _as_colmajor(a):
+    """(ptr, m, n, lda) of a 2-D tensor as a column-major matrix with the same singular values."""
+    m, n = a.shape
+    if a.stride(0) == 1 and a.stride(1) >= max(1, m):
+        return a, m, n, a.stride(1)
+    a = a.contiguous()
+    # row-major (m, n) == column-major (n, m) = A^T
+    return a, n, m, max(1, n)
+
+
+def default_config(m: int, n: int, dtype: str = "float32") -> Config:
+    c = _Config()
+    _check(lib().svdv_default_config(m, n, SVDV_F32 if dtype == "float32" else SVDV_F64, ctypes.byref(c)))
+    return Config(c.tile, c.threads, c.inner_block, c.sweep_width, c.update_precision)
+
+
+def check_config(m: int, n: int, dtype: str, cfg) -> bool:
+    """True if cfg is runnable for (m, n, dtype); False if the library reports it unsupported."""
+    rc = lib().svdv_check_config(m, n, SVDV_F32 if dtype == "float32" else SVDV_F64, _cfg_ptr(cfg))
+    if rc == -2:
+        return False
+    _check(rc)
+    return True
+
+
+def svd_values(a, config=None, out=None):
+    """Singular values (descending) of the 2-D CUDA tensor ``a`` (float32/float64)."""
+    torch = _torch()
+    if a.dim() != 2 or not a.is_cuda:
+        raise ValueError("expected a 2-D tensor on a GPU")
+    dt = _dtype_code(a)
+    a2, m, n, lda = _as_colmajor(a)
+    k = min(m, n)
+    s = out if out is not None else torch.empty(k, dtype=a.dtype, device=a.device)
+    _check(lib().svd_values_ex(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(s.data_ptr()),
+                               _stream(a.device), _cfg_ptr(config)))
+    return s
+
+
+def svd_values_batched(mats, config=None):
+    """Singular values of a list of 2-D CUDA tensors (same dtype, uneven sizes) in one call.
+
+    Returns (packed values, offsets): matrix i's values are packed[offsets[i]:offsets[i]+min(m_i,n_i)]."""
+    torch = _torch()
+    if not mats:
+        return None, []
+    dt = _dtype_code(mats[0])
+    keep, ptrs, ms, ns, ldas, offs = [], [], [], [], [], []
+    off = 0
+    for a in mats:
+        a2, m, n, lda = _as_colmajor(a)
+        keep.append(a2)
+        ptrs.append(a2.data_ptr())
+        ms.append(m)
+        ns.append(n)
+        ldas.append(lda)
+        offs.append(off)
+        off += min(m, n)
+    s = torch.empty(max(off, 1), dtype=mats[0].dtype, device=mats[0].device)
+    B = len(mats)
+    P = (ctypes.c_void_p * B)(*ptrs)
+    I64 = ctypes.c_int64 * B
+    _check(lib().svd_values_batched(ctypes.cast(P, ctypes.c_void_p), ctypes.cast(I64(*ms), ctypes.c_void_p),
+                                    ctypes.cast(I64(*ns), ctypes.c_void_p), ctypes.cast(I64(*ldas), ctypes.c_void_p),
+                                    B, dt, ctypes.c_void_p(s.data_ptr()), ctypes.cast(I64(*offs), ctypes.c_void_p),
+                                    _stream(mats[0].device), _cfg_ptr(config)))
+    return s, offs
+
+
+def stage_band(a, config=None):
+    """Stage 1 only: the (k, tile+1) float64 band, row i = B(i, i..i+tile), k = min(m, n)."""
+    torch = _torch()
+    dt = _dtype_code(a)
+    cfg = config if config is not None else default_config(*a.shape, "float32" if dt == SVDV_F32 else "float64")
+    if isinstance(cfg, dict):
+        cfg = Config(**cfg)
+    a2, m, n, lda = _as_colmajor(a)
+    k = min(m, n)
+    band = torch.zeros((k, cfg.tile + 1), dtype=torch.float64, device=a.device)
+    _check(lib().svdv_stage_band(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(band.data_ptr()),
+                                 cfg.tile + 1, _stream(a.device), _cfg_ptr(cfg)))
+    return band
+
+
+def stage_bidiag(band, b: int, config=None):
+    """Stage 2 only: (d, e) of the bidiagonal from a (n, >= b+1) float64 band tensor."""
+    torch = _torch()
+    n = band.shape[0]
+    band = band.contiguous()
+    d = torch.empty(n, dtype=torch.float64, device=band.device)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=band.device)
+    _check(lib().svdv_stage_bidiag(ctypes.c_void_p(band.data_ptr()), n, b, band.shape[1],
+                                   ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+                                   _stream(band.device), _cfg_ptr(config)))
+    return d, e[: max(n - 1, 0)]
+
+
+def stage_values(d, e, out_dtype=None):
+    """Stage 3 only: singular values (descending) of the upper bidiagonal (d, e) (float64 tensors)."""
+    torch = _torch()
+    out_dtype = out_dtype or torch.float64
+    n = d.shape[0]
+    s = torch.empty(n, dtype=out_dtype, device=d.device)
+    e2 = e.contiguous() if e.numel() else d
+    _check(lib().svdv_stage_values(ctypes.c_void_p(d.contiguous().data_ptr()), ctypes.c_void_p(e2.data_ptr()), n,
+                                   SVDV_F32 if out_dtype == torch.float32 else SVDV_F64,
+                                   ctypes.c_void_p(s.data_ptr()), _stream(d.device)))
+    return s
+
+
+def apply_qt(V, T, C, side: int = 0, config=None):
+    """The stage-1 trailing-update kernel alone: C <- (I - V T V^T)^T C (side 0) or C (I - V T V^T) (side 1).
+
+    V, T, C are column-major CUDA tensors given as torch views of their transposes is NOT assumed:
+    pass tensors whose .T is contiguous (i.e. Fortran order), e.g. ``x.t().contiguous().t()``."""
+    dt = _dtype_code(C)
+    for x in (V, T, C):
+        if x.stride(0) != 1:
+            raise ValueError("apply_qt expects column-major (Fortran-order) tensors")
+    h, w = C.shape
+    k = V.shape[1]
+    _check(lib().svdv_apply_qt(ctypes.c_void_p(V.data_ptr()), V.stride(1), ctypes.c_void_p(T.data_ptr()),
+                               T.stride(1), ctypes.c_void_p(C.data_ptr()), C.stride(1), h, w, k, dt, side,
+                               _stream(C.device), _cfg_ptr(config)))
+    return C
+
+
+def release():
+    _check(lib().svdv_release())

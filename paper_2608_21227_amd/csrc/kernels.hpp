@@ -1,0 +1,95 @@
+// Kernel argument blocks, compile-time configuration tables and launcher
+// declarations shared by the stage sources and the host pipeline.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.hpp"
+
+namespace svdv {
+
+// Rows per lane of the chunk-QR kernel (16 waves, one chunk in registers):
+// 64 * RPT rows * TILE columns = 32 elements per thread.
+template <int TILE> struct ChunkRPT { static constexpr int value = 512 / TILE; };
+
+template <typename T>
+struct ChunkQRArgs {
+  View<T> M;          // matrix view holding the panel (column-major or transposed)
+  int64_t pc;         // first panel column (view coordinates)
+  int32_t bw;         // panel width
+  RowMap rm;          // rows of chunk c
+  int64_t h;          // total rows at this tree level
+  int64_t chunk_rows; // rows per chunk (the last chunk takes the remainder)
+  int32_t P;          // chunks at this level
+  T* V;               // Householder vectors, chunk c at rows [c*chunk_rows, ...), leading dim ldv
+  int64_t ldv;
+  T* Tm;              // compact-WY factors, chunk c at Tm + c*TILE*TILE (TILE x TILE column-major)
+};
+
+template <typename T>
+struct LarfbArgs {
+  View<T> M;          // matrix view holding C
+  RowMap rm;          // rows of chunk c (same map as the factorisation of that level)
+  int64_t h, chunk_rows;
+  int32_t P;
+  int64_t col0, col1; // view columns to update
+  const T* V;
+  int64_t ldv;
+  const T* Tm;
+  int64_t ldt;        // = TILE (per-chunk T is ldt x ldt)
+  int32_t k;          // reflectors per chunk
+};
+
+// Register estimate (32-bit registers per lane) of the trailing-update kernel:
+// Z and Z' accumulators (KT x IB tiles), the C tile (IB), the V operand (KT).
+template <typename T>
+constexpr int larfb_regs(int KT, int IB) {
+  return (2 * KT * IB * 4 + IB * 4 + KT * 4 + 20) * (int)(sizeof(T) / 4);
+}
+constexpr int larfb_budget(int NW) { return NW >= 16 ? 128 : 256; }
+template <typename T>
+constexpr bool larfb_valid(int KT, int IB, int NW) {
+  return larfb_regs<T>(KT, IB) <= larfb_budget(NW) && !(sizeof(T) == 8 && KT > 4);
+}
+
+// Fill kernels (used instead of hipMemsetAsync so that every step can be captured in a graph).
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n);
+__global__ void k_fill_i32(int* p, int v, int64_t n);
+__global__ void k_fill_f64(double* p, double v, int64_t n);
+
+template <typename T>
+hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int transpose, T* W, int64_t ldw,
+                           unsigned long long* amax, int* exp_out, hipStream_t st);
+template <typename T> int chunk_qr_hmax(int tile);
+template <typename T> hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st);
+template <typename T> hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,
+                            int unscale, hipStream_t st);
+template <typename T>
+hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double* out, int64_t ldo, const int* exp_in,
+                               hipStream_t st);
+hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, hipStream_t st);
+
+// Stage 2.
+struct ChaseArgs {
+  double* Bs;          // chase storage, row-major, row i at Bs + i*ldb; column j at offset j - i + (b-1)
+  int64_t ldb;
+  int64_t n;
+  int32_t b;
+  int32_t W;           // sweeps per workgroup (sweep width)
+  int32_t ngroups;     // ceil((n-1) / W)
+  int32_t* progress;   // per group: tasks completed by its last sweep (n entries, zeroed before launch)
+  int32_t* err;        // set when a bounded wait gives up
+  double* d;
+  double* e;
+};
+size_t chase_lds_bytes(int b, int W);
+int chase_max_groups_resident(int b, int W);
+hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st);
+
+// Stage 3.
+template <typename T>
+hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in,
+                         int lanes_per_value, hipStream_t st);
+
+}  // namespace svdv

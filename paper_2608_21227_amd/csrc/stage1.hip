@@ -1,0 +1,583 @@
+// Stage 1 of the two-stage singular-value method: reduction of a dense matrix to
+// upper band form with bandwidth TS (Algorithm 1 of the paper).  For every
+// diagonal tile k: QR sweep (panel factorisation of the tile column, then the
+// trailing update from the left) and LQ sweep (the same on the tile row, applied
+// from the right).  The LQ sweep runs the same kernels on the transposed view.
+//
+// Panel factorisation (the paper's GEQRT/TSQRT step): a tall-skinny QR done as a
+// tree.  Level-1 chunks of up to 64*RPT rows are factored independently, one
+// workgroup each, with the chunk held in registers; the R factors of a level are
+// stacked and factored again at the next level until one chunk remains.  Every
+// level stores its Householder vectors V (unit lower trapezoidal) and the
+// compact-WY factor T (Q = I - V T V^T).
+//
+// Trailing update (the paper's UNMQR/TSMQR step, Algorithm 2): C <- Q^T C per
+// chunk and per level, in compact-WY form C -= V (T^T (V^T C)), with the three
+// products on the MFMA units.  Each wave owns IB 16-column tiles and walks the
+// chunk's rows twice (V^T C, then the rank-k update); nothing is shared between
+// waves, so no LDS and no barriers are needed.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace svdv {
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i32(int* p, int v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// a1: input staging -- max |a|, then copy (optionally transposed) scaled by 2^-e
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long abs_bits(double x) {
+  return (unsigned long long)__double_as_longlong(fabs(x));
+}
+
+template <typename T>
+__global__ void k_absmax(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, unsigned long long* out) {
+  double mx = 0.0;
+  int64_t total = m * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = idx / m, i = idx - j * m;
+    double v = fabs((double)A[i + j * lda]);
+    if (!(v <= mx)) mx = v;  // NaN wins
+  }
+  unsigned long long b = abs_bits(mx);
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(b, off, kWave);
+    b = o > b ? o : b;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, b);
+}
+
+// exponent e with max*2^-e in [0.5, 1); 0 if max is zero or not finite
+__device__ __forceinline__ int scale_exponent(unsigned long long bits) {
+  double mx = __longlong_as_double((long long)bits);
+  if (!(mx > 0.0) || !isfinite(mx)) return 0;
+  int e;
+  frexp(mx, &e);
+  return e;
+}
+
+template <typename T>
+__global__ void k_copy_scale(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, int transpose,
+                             T* __restrict__ W, int64_t ldw, const unsigned long long* amax, int* exp_out) {
+  int e = scale_exponent(*amax);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
+  // W is M x N with M = transpose ? n : m
+  int64_t M = transpose ? n : m, N = transpose ? m : n;
+  int64_t total = M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = idx / M, i = idx - j * M;
+    T v = transpose ? A[j + i * lda] : A[i + j * lda];
+    W[i + j * ldw] = (T)ldexp((double)v, -e);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2/a4: chunk QR (one TSQR chunk per workgroup, chunk in registers)
+// ---------------------------------------------------------------------------
+//
+// Thread layout: NW = 16 waves; wave w owns columns [w*CPT, (w+1)*CPT); lane l
+// owns rows q = i*64 + l, i < RPT.  Column sums are wave reductions.
+
+template <typename T, int TILE, int RPT>
+struct ChunkQRCfg {
+  static constexpr int NW = 16;
+  static constexpr int CPT = TILE / NW;
+  static constexpr int HMAX = 64 * RPT;
+};
+
+template <typename T, int TILE, int RPT>
+__global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
+  typedef ChunkQRCfg<T, TILE, RPT> C;
+  constexpr int CPT = C::CPT;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int c = blockIdx.x;
+  const int64_t row0 = (int64_t)c * a.chunk_rows;
+  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
+  const int bw = a.bw;
+  const int kr = Hc < bw ? Hc : bw;
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // LDS: stage tile [64][TILE+1] (also reused as Mtmp at the end) | vbuf[2][HMAX] | taus[TILE] | Tl[TILE][TILE+1]
+  T* stage = reinterpret_cast<T*>(smem_raw);
+  T* Mtmp = stage;
+  T* vbuf = stage + 64 * (TILE + 1);
+  T* taus = vbuf + 2 * C::HMAX;
+  T* Tl = taus + TILE;
+  constexpr int LDT = TILE + 1;
+
+  T x[RPT][CPT];
+
+  // ---- load the chunk through LDS (coalesced along the memory-contiguous direction) ----
+  const bool rows_contig = (a.M.rs == 1);
+  for (int i = 0; i < RPT; ++i) {
+    const int qb = i * 64;
+    if (qb >= Hc) {  // uniform
+#pragma unroll
+      for (int cc = 0; cc < CPT; ++cc) x[i][cc] = T(0);
+      continue;
+    }
+    for (int t = threadIdx.x; t < 64 * TILE; t += 1024) {
+      int r, col;
+      if (rows_contig) { col = t >> 6; r = t & 63; } else { r = t / TILE; col = t - r * TILE; }
+      const int q = qb + r;
+      T v = T(0);
+      if (q < Hc && col < bw) {
+        const int64_t gr = a.rm.row(c, q);
+        v = a.M.at(gr, a.pc + col);
+        if (a.rm.per_unit != 0 && (q % a.rm.per_unit) > col) v = T(0);
+      }
+      stage[r * (TILE + 1) + col] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) x[i][cc] = stage[l * (TILE + 1) + w * CPT + cc];
+    __syncthreads();
+  }
+
+  // ---- Householder loop over the panel columns ----
+  for (int j = 0; j < kr; ++j) {
+    const int ow = j / CPT, oc = j % CPT;
+    T* vb = vbuf + (j & 1) * C::HMAX;
+    if (w == ow) {
+      double ss = 0.0, alpha_l = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int q = i * 64 + l;
+        double v = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) if (cc == oc) v = (double)x[i][cc];
+        if (q > j) ss += v * v;
+        if (q == j) alpha_l = v;
+      }
+      ss = wave_sum(ss);
+      const double alpha = __shfl(alpha_l, j & 63, kWave);
+      double beta = alpha, tau = 0.0, scal = 0.0;
+      if (ss > 0.0) {
+        const double nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int q = i * 64 + l;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+          if (cc != oc) continue;
+          T v = x[i][cc];
+          T vv;
+          if (q > j) { v = (T)((double)v * scal); vv = v; }
+          else if (q == j) { vv = T(1); v = (T)beta; }
+          else vv = T(0);
+          x[i][cc] = v;
+          vb[q] = vv;
+        }
+      }
+      if (l == 0) { taus[j] = (T)tau; Tl[j * LDT + j] = (T)tau; }
+    }
+    __syncthreads();
+    const T tau = taus[j];
+    T vr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) vr[i] = vb[i * 64 + l];
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+      const int gc = w * CPT + cc;
+      if (gc == j || gc >= bw) continue;
+      T d = T(0);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += vr[i] * x[i][cc];
+      d = wave_sum(d);
+      if (gc > j) {
+        const T td = tau * d;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) x[i][cc] -= td * vr[i];
+      } else if (l == 0) {
+        Tl[gc * LDT + j] = d;  // Y[gc][j] = v_gc^T v_j
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- compact-WY factor: T = inverse of (diag(1/tau) + strict upper of V^T V), by doubling ----
+  for (int bs = 1; bs < kr; bs *= 2) {
+    const int npair = (kr + 2 * bs - 1) / (2 * bs);
+    // M = Y_AB * T_BB
+    for (int t = threadIdx.x; t < npair * bs * bs; t += blockDim.x) {
+      const int p = t / (bs * bs), r = (t / bs) % bs, cidx = t % bs;
+      const int i0 = p * 2 * bs, ia = i0 + r, ib = i0 + bs + cidx;
+      T s = T(0);
+      if (ib < kr) {
+        for (int lq = i0 + bs; lq <= ib; ++lq) s += Tl[ia * LDT + lq] * Tl[lq * LDT + ib];
+      }
+      Mtmp[t] = s;
+    }
+    __syncthreads();
+    // T_AB = -T_AA * M
+    for (int t = threadIdx.x; t < npair * bs * bs; t += blockDim.x) {
+      const int p = t / (bs * bs), r = (t / bs) % bs, cidx = t % bs;
+      const int i0 = p * 2 * bs, ia = i0 + r, ib = i0 + bs + cidx;
+      if (ib < kr) {
+        T s = T(0);
+        for (int lq = ia; lq < i0 + bs; ++lq) s += Tl[ia * LDT + lq] * Mtmp[p * bs * bs + (lq - i0) * bs + cidx];
+        Tl[ia * LDT + ib] = -s;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- outputs: T (TILE x TILE, column-major, zero outside kr), V, R ----
+  T* Tout = a.Tm + (int64_t)c * TILE * TILE;
+  for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+    const int r = t % TILE, col = t / TILE;
+    Tout[t] = (r < kr && col < kr && r <= col) ? Tl[r * LDT + col] : T(0);
+  }
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int gc = w * CPT + cc;
+    if (gc >= kr) continue;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int q = i * 64 + l;
+      if (q >= Hc) continue;
+      const T v = q > gc ? x[i][cc] : (q == gc ? T(1) : T(0));
+      a.V[(row0 + q) + (int64_t)gc * a.ldv] = v;
+    }
+  }
+  // R: upper triangle of the top kr rows (q <= gc, q < kr), all bw columns.
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int gc = w * CPT + cc;
+    if (gc >= bw) continue;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int q = i * 64 + l;
+      if (q < kr && q <= gc) a.M.at(a.rm.row(c, q), a.pc + gc) = x[i][cc];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3/a5: trailing update  C <- (I - V T V^T)^T C  on MFMA
+// ---------------------------------------------------------------------------
+
+// Row of the 16x16 MFMA result held in register i of lane-group g (g = lane / 16):
+// float: 4g + i, double: 4i + g (measured on gfx950).
+template <typename T> __device__ __forceinline__ int acc_row(int g, int i);
+template <> __device__ __forceinline__ int acc_row<float>(int g, int i) { return 4 * g + i; }
+template <> __device__ __forceinline__ int acc_row<double>(int g, int i) { return 4 * i + g; }
+
+template <typename T, int KT, int IB, int NW>
+__global__ void __launch_bounds__(NW * 64) k_larfb(LarfbArgs<T> a) {
+  typedef typename Acc<T>::type AccT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NWv = NW;
+  const int g = lane >> 4, nl = lane & 15;
+  const int c = blockIdx.y;
+  const int64_t row0 = (int64_t)c * a.chunk_rows;
+  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
+  const int k = a.k;
+  const int64_t colbase = a.col0 + ((int64_t)blockIdx.x * NWv + wv) * (IB * 16);
+  if (colbase >= a.col1) return;  // whole wave idle (no barriers in this kernel)
+  const T* V = a.V + row0;
+  const T* Tm = a.Tm + (int64_t)c * a.ldt * a.ldt;
+
+  AccT Z[KT][IB];
+#pragma unroll
+  for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+
+  const int nslab = (Hc + 15) >> 4;
+  // ---- pass 1: Z = V^T C ----
+  for (int s = 0; s < nslab; ++s) {
+    T cb[IB][4], av[KT][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = s * 16 + acc_row<T>(g, i);
+      const bool rok = q < Hc;
+      const int64_t gr = rok ? a.rm.row(c, q) : 0;
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) {
+        const int64_t col = colbase + nt * 16 + nl;
+        cb[nt][i] = (rok && col < a.col1) ? a.M.at(gr, col) : T(0);
+      }
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt) {
+        const int r = mt * 16 + nl;
+        av[mt][i] = (rok && r < k) ? V[q + (int64_t)r * a.ldv] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(av[mt][i], cb[nt][i], Z[mt][nt]);
+  }
+
+  // ---- Z' = T^T Z ----
+  AccT Zp[KT][IB];
+#pragma unroll
+  for (int ot = 0; ot < KT; ++ot)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) Zp[ot][nt] = AccT{0, 0, 0, 0};
+#pragma unroll
+  for (int ot = 0; ot < KT; ++ot) {
+#pragma unroll
+    for (int mt = 0; mt < KT; ++mt) {
+      if (mt > ot) continue;  // T upper triangular: T[in][out] = 0 for in > out
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rin = mt * 16 + acc_row<T>(g, i), rout = ot * 16 + nl;
+        const T tv = (rin < k && rout < k) ? Tm[rin + (int64_t)rout * a.ldt] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) Zp[ot][nt] = mfma16(tv, Z[mt][nt][i], Zp[ot][nt]);
+      }
+    }
+  }
+
+  // ---- pass 2: C -= V Z' ----
+  for (int s = 0; s < nslab; ++s) {
+    AccT cd[IB];
+    int64_t grow[4];
+    bool rok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = s * 16 + acc_row<T>(g, i);
+      rok[i] = q < Hc;
+      grow[i] = rok[i] ? a.rm.row(c, q) : 0;
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) {
+        const int64_t col = colbase + nt * 16 + nl;
+        cd[nt][i] = (rok[i] && col < a.col1) ? a.M.at(grow[i], col) : T(0);
+      }
+    }
+    const int qa = s * 16 + nl;  // A-operand row (V row)
+    const bool aok = qa < Hc;
+#pragma unroll
+    for (int ot = 0; ot < KT; ++ot) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = ot * 16 + acc_row<T>(g, i);
+        const T vv = (aok && r < k) ? -V[qa + (int64_t)r * a.ldv] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) cd[nt] = mfma16(vv, Zp[ot][nt][i], cd[nt]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!rok[i]) continue;
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) {
+        const int64_t col = colbase + nt * 16 + nl;
+        if (col < a.col1) a.M.at(grow[i], col) = cd[nt][i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a6: band pack -- W (dtype T, column-major) -> chase storage (float64, row-major,
+// row i holds columns i-(b-1) .. i+2b-1 at offsets 0 .. 3b-2; width ldb)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_band_pack(const T* __restrict__ W, int64_t ldw, int64_t n, int b, double* __restrict__ Bs, int64_t ldb,
+                            const int* exp_in, int unscale) {
+  const int64_t total = n * ldb;
+  const int e = unscale ? *exp_in : 0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / ldb;
+    const int d = (int)(idx - i * ldb);
+    const int64_t j = i + d - (b - 1);
+    double v = 0.0;
+    if (j >= i && j <= i + b && j < n) v = ldexp((double)W[i + j * ldw], e);
+    Bs[idx] = v;
+  }
+}
+
+// External band layout (band[i*ldband + d] = B(i, i+d), d = 0..b) <-> chase storage.
+template <typename T>
+__global__ void k_band_extract(const T* __restrict__ W, int64_t ldw, int64_t n, int b, double* __restrict__ out,
+                               int64_t ldo, const int* exp_in) {
+  const int64_t total = n * (b + 1);
+  const int e = *exp_in;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / (b + 1);
+    const int d = (int)(idx - i * (b + 1));
+    const int64_t j = i + d;
+    out[i * ldo + d] = j < n ? ldexp((double)W[i + j * ldw], e) : 0.0;
+  }
+}
+
+__global__ void k_band_import(const double* __restrict__ in, int64_t ldi, int64_t n, int b, double* __restrict__ Bs,
+                              int64_t ldb) {
+  const int64_t total = n * ldb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / ldb;
+    const int d = (int)(idx - i * ldb);
+    const int64_t off = d - (b - 1);
+    Bs[idx] = (off >= 0 && off <= b && i + off < n) ? in[i * ldi + off] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+static inline int grid_for(int64_t total, int block) {
+  int64_t g = (total + block - 1) / block;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename T>
+hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int transpose, T* W, int64_t ldw,
+                           unsigned long long* amax, int* exp_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, amax, 1ull * 0, (int64_t)1);
+  hipLaunchKernelGGL(k_absmax<T>, dim3(grid_for(m * n, 256)), dim3(256), 0, st, A, m, n, lda, amax);
+  hipLaunchKernelGGL(k_copy_scale<T>, dim3(grid_for(m * n, 256)), dim3(256), 0, st, A, m, n, lda, transpose, W, ldw,
+                     amax, exp_out);
+  return hipGetLastError();
+}
+
+template <typename T, int TILE, int RPT>
+static size_t chunk_qr_lds() {
+  return sizeof(T) * (64 * (TILE + 1) + 2 * 64 * RPT + TILE + TILE * (TILE + 1));
+}
+
+template <typename T, int TILE, int RPT>
+static hipError_t launch_cqr(const ChunkQRArgs<T>& a, hipStream_t st) {
+  if constexpr (sizeof(T) == 8 && TILE > 64) {
+    return hipErrorInvalidConfiguration;
+  } else {
+  const size_t lds = chunk_qr_lds<T, TILE, RPT>();
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr<T, TILE, RPT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  hipLaunchKernelGGL((k_chunk_qr<T, TILE, RPT>), dim3(a.P), dim3(1024), lds, st, a);
+  return hipGetLastError();
+  }
+}
+
+template <typename T>
+int chunk_qr_hmax(int tile) {
+  switch (tile) {
+    case 16: return 64 * ChunkRPT<16>::value;
+    case 32: return 64 * ChunkRPT<32>::value;
+    case 64: return 64 * ChunkRPT<64>::value;
+    case 128: return 64 * ChunkRPT<128>::value;
+  }
+  return 0;
+}
+template int chunk_qr_hmax<float>(int);
+template int chunk_qr_hmax<double>(int);
+
+template <typename T>
+hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st) {
+  switch (tile) {
+    case 16: return launch_cqr<T, 16, ChunkRPT<16>::value>(a, st);
+    case 32: return launch_cqr<T, 32, ChunkRPT<32>::value>(a, st);
+    case 64: return launch_cqr<T, 64, ChunkRPT<64>::value>(a, st);
+    case 128: return launch_cqr<T, 128, ChunkRPT<128>::value>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int KT, int IB, int NW>
+static hipError_t launch_larfb_nw(const LarfbArgs<T>& a, hipStream_t st) {
+  if constexpr (larfb_valid<T>(KT, IB, NW)) {
+    const int64_t ncols = a.col1 - a.col0;
+    const int64_t per_block = (int64_t)NW * IB * 16;
+    const dim3 grid((unsigned)((ncols + per_block - 1) / per_block), (unsigned)a.P);
+    hipLaunchKernelGGL((k_larfb<T, KT, IB, NW>), grid, dim3(NW * 64), 0, st, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidConfiguration;
+  }
+}
+
+template <typename T, int KT, int IB>
+static hipError_t launch_larfb_ib(int nw, const LarfbArgs<T>& a, hipStream_t st) {
+  switch (nw) {
+    case 1: return launch_larfb_nw<T, KT, IB, 1>(a, st);
+    case 2: return launch_larfb_nw<T, KT, IB, 2>(a, st);
+    case 4: return launch_larfb_nw<T, KT, IB, 4>(a, st);
+    case 8: return launch_larfb_nw<T, KT, IB, 8>(a, st);
+    case 16: return launch_larfb_nw<T, KT, IB, 16>(a, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T, int KT>
+static hipError_t launch_larfb_kt(int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
+  switch (ib) {
+    case 1: return launch_larfb_ib<T, KT, 1>(nw, a, st);
+    case 2: return launch_larfb_ib<T, KT, 2>(nw, a, st);
+    case 4: return launch_larfb_ib<T, KT, 4>(nw, a, st);
+    case 8: return launch_larfb_ib<T, KT, 8>(nw, a, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T>
+hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
+  if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
+  switch (tile) {
+    case 16: return launch_larfb_kt<T, 1>(nw, ib, a, st);
+    case 32: return launch_larfb_kt<T, 2>(nw, ib, a, st);
+    case 64: return launch_larfb_kt<T, 4>(nw, ib, a, st);
+    case 128: return launch_larfb_kt<T, 8>(nw, ib, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,
+                            int unscale, hipStream_t st) {
+  hipLaunchKernelGGL(k_band_pack<T>, dim3(grid_for(n * ldb, 256)), dim3(256), 0, st, W, ldw, n, b, Bs, ldb, exp_in,
+                     unscale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double* out, int64_t ldo, const int* exp_in,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_band_extract<T>, dim3(grid_for(n * (b + 1), 256)), dim3(256), 0, st, W, ldw, n, b, out, ldo,
+                     exp_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, hipStream_t st) {
+  hipLaunchKernelGGL(k_band_import, dim3(grid_for(n * ldb, 256)), dim3(256), 0, st, in, ldi, n, b, Bs, ldb);
+  return hipGetLastError();
+}
+
+#define SVDV_INST(T)                                                                                             \
+  template hipError_t launch_stage_in<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t, unsigned long long*, \
+                                         int*, hipStream_t);                                                      \
+  template hipError_t launch_chunk_qr<T>(int, const ChunkQRArgs<T>&, hipStream_t);                               \
+  template hipError_t launch_larfb<T>(int, int, int, const LarfbArgs<T>&, hipStream_t);                          \
+  template hipError_t launch_band_pack<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*, int,     \
+                                          hipStream_t);                                                           \
+  template hipError_t launch_band_extract<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*,       \
+                                             hipStream_t);
+SVDV_INST(float)
+SVDV_INST(double)
+
+}  // namespace svdv

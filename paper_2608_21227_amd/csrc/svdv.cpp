@@ -1,0 +1,542 @@
+// Host side of the svdv C-ABI: argument validation, configuration checks, the
+// stage-1 panel/update schedule (Algorithm 1) with its TSQR tree plan, the
+// per-(device, stream) workspace cache and the dispatch to the HIP kernels.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/svdv.h"
+#include "kernels.hpp"
+
+using namespace svdv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+int fail_hip(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return SVDV_ERR_HIP;
+}
+#define HIPCHK(expr)                              \
+  do {                                            \
+    hipError_t _e = (expr);                       \
+    if (_e != hipSuccess) return fail_hip(_e, #expr); \
+  } while (0)
+
+bool is_pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int elem_size(int dtype) { return dtype == SVDV_F32 ? 4 : 8; }
+
+// ----------------------------------------------------------------------------
+// configuration
+// ----------------------------------------------------------------------------
+
+template <typename T>
+bool larfb_ok(int tile, int threads, int ib) {
+  const int KT = tile / 16, NW = threads / 64;
+  return larfb_valid<T>(KT, ib, NW);
+}
+
+int check_config_impl(int64_t m, int64_t n, int dtype, const svdv_config& c) {
+  if (dtype != SVDV_F32 && dtype != SVDV_F64) return fail(SVDV_ERR_INVALID_ARG, "dtype must be SVDV_F32 or SVDV_F64");
+  if (!(c.tile == 16 || c.tile == 32 || c.tile == 64 || c.tile == 128))
+    return fail(SVDV_ERR_UNSUPPORTED, "tile must be one of 16, 32, 64, 128");
+  if (!is_pow2_in(c.threads, 64, 1024)) return fail(SVDV_ERR_UNSUPPORTED, "threads must be 64, 128, 256, 512 or 1024");
+  if (!(c.inner_block == 1 || c.inner_block == 2 || c.inner_block == 4 || c.inner_block == 8))
+    return fail(SVDV_ERR_UNSUPPORTED, "inner_block must be 1, 2, 4 or 8");
+  if (c.sweep_width < 1 || c.sweep_width > 8) return fail(SVDV_ERR_UNSUPPORTED, "sweep_width must be in 1..8");
+  if (c.update_precision != 0) return fail(SVDV_ERR_UNSUPPORTED, "update_precision other than 0 is not built");
+  if (dtype == SVDV_F64 && c.tile > 64) return fail(SVDV_ERR_UNSUPPORTED, "float64 supports tiles up to 64");
+  const bool ok = dtype == SVDV_F32 ? larfb_ok<float>(c.tile, c.threads, c.inner_block)
+                                    : larfb_ok<double>(c.tile, c.threads, c.inner_block);
+  if (!ok) return fail(SVDV_ERR_UNSUPPORTED, "trailing-update tile exceeds the register budget for this workgroup size");
+  if (chase_lds_bytes(c.tile, c.sweep_width) > 160 * 1024 - 1024)
+    return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase LDS exceeds 160 KiB for this tile and sweep width");
+  (void)m;
+  (void)n;
+  return SVDV_OK;
+}
+
+svdv_config default_config(int64_t m, int64_t n, int dtype) {
+  (void)m;
+  svdv_config c;
+  c.tile = 32;
+  c.threads = 256;
+  c.inner_block = 2;
+  c.sweep_width = 4;
+  c.update_precision = 0;
+  (void)n;
+  (void)dtype;
+  return c;
+}
+
+// ----------------------------------------------------------------------------
+// TSQR tree plan for one panel of height h and width bw
+// ----------------------------------------------------------------------------
+
+struct Level {
+  int64_t h;           // rows at this level
+  int64_t chunk_rows;  // rows per chunk
+  int32_t P;           // chunks
+  RowMap rm;
+  int64_t voff;        // offset (elements) of this level's V in the V workspace
+  int64_t toff;        // offset (elements) of this level's T factors
+};
+
+std::vector<Level> plan_panel(int64_t r0, int64_t h, int bw, int tile, int hmax) {
+  std::vector<Level> L;
+  int64_t voff = 0, toff = 0;
+  // level 1
+  int64_t P = 1, cr = h;
+  if (h > hmax) {
+    for (P = (h + hmax - 1) / hmax;; ++P) {
+      cr = ((h + P - 1) / P + 15) / 16 * 16;
+      if (cr > hmax) continue;
+      const int64_t rem = h - (P - 1) * cr;
+      if (rem >= bw && rem <= hmax && rem > 0) break;
+    }
+  }
+  Level l1;
+  l1.h = h;
+  l1.chunk_rows = cr;
+  l1.P = (int32_t)P;
+  l1.rm = RowMap{r0, cr, 0, 0};
+  l1.voff = voff;
+  l1.toff = toff;
+  voff += h * tile;
+  toff += P * (int64_t)tile * tile;
+  L.push_back(l1);
+  int64_t U = cr;  // matrix rows between consecutive chunk tops of the previous level
+  const int64_t F = hmax / bw;
+  while (L.back().P > 1) {
+    const int64_t units = L.back().P;
+    Level lv;
+    lv.h = units * bw;
+    if (lv.h <= hmax) {
+      lv.P = 1;
+      lv.chunk_rows = lv.h;
+      lv.rm = RowMap{r0, 0, U, bw};
+    } else {
+      lv.P = (int32_t)((units + F - 1) / F);
+      lv.chunk_rows = F * bw;
+      lv.rm = RowMap{r0, F * U, U, bw};
+    }
+    lv.voff = voff;
+    lv.toff = toff;
+    voff += lv.h * tile;
+    toff += (int64_t)lv.P * tile * tile;
+    L.push_back(lv);
+    U = (lv.P > 1) ? F * U : U;
+  }
+  return L;
+}
+
+void panel_ws(int64_t h, int bw, int tile, int hmax, int64_t* vsz, int64_t* tsz) {
+  auto L = plan_panel(0, h, bw, tile, hmax);
+  int64_t v = 0, t = 0;
+  for (auto& l : L) {
+    v += l.h * tile;
+    t += (int64_t)l.P * tile * tile;
+  }
+  *vsz = v;
+  *tsz = t;
+}
+
+// ----------------------------------------------------------------------------
+// workspace
+// ----------------------------------------------------------------------------
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_mu;
+std::map<std::pair<int, void*>, Workspace> g_ws;
+
+int get_workspace(void* stream, size_t bytes, char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace& w = g_ws[{dev, stream}];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+      HIPCHK(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) {
+      w.ptr = nullptr;
+      return fail(SVDV_ERR_NO_MEMORY, std::string("workspace hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    w.bytes = bytes;
+  }
+  *out = (char*)w.ptr;
+  return SVDV_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+  size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, total;
+};
+
+Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_width, int64_t ldw) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  int64_t vsz = 0, tsz = 0;
+  panel_ws(M, std::min<int64_t>(tile, N), tile, hmax, &vsz, &tsz);
+  L.W = take((size_t)ldw * N * es);
+  L.V = take((size_t)vsz * es);
+  L.T = take((size_t)tsz * es);
+  L.Bs = take((size_t)N * 3 * tile * 8);
+  const int64_t ngroups = (N + sweep_width - 1) / sweep_width + 1;
+  L.progress = take((size_t)(ngroups + 1) * 4);
+  L.err = take(8);
+  L.amax = take(8);
+  L.exp = take(8);
+  L.d = take((size_t)N * 8);
+  L.e = take((size_t)N * 8);
+  L.work = take((size_t)(2 * N + 2) * 8);
+  L.total = off;
+  return L;
+}
+
+// ----------------------------------------------------------------------------
+// stage 1 driver
+// ----------------------------------------------------------------------------
+
+template <typename T>
+int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t ncols, const svdv_config& cfg,
+                   T* vws, T* tws, hipStream_t st) {
+  const int hmax = chunk_qr_hmax<T>(cfg.tile);
+  auto levels = plan_panel(r0, h, bw, cfg.tile, hmax);
+  for (auto& lv : levels) {
+    ChunkQRArgs<T> a;
+    a.M = V;
+    a.pc = pc;
+    a.bw = bw;
+    a.rm = lv.rm;
+    a.h = lv.h;
+    a.chunk_rows = lv.chunk_rows;
+    a.P = lv.P;
+    a.V = vws + lv.voff;
+    a.ldv = lv.h;
+    a.Tm = tws + lv.toff;
+    HIPCHK(launch_chunk_qr<T>(cfg.tile, a, st));
+  }
+  if (pc + bw < ncols) {
+    for (auto& lv : levels) {
+      LarfbArgs<T> a;
+      a.M = V;
+      a.rm = lv.rm;
+      a.h = lv.h;
+      a.chunk_rows = lv.chunk_rows;
+      a.P = lv.P;
+      a.col0 = pc + bw;
+      a.col1 = ncols;
+      a.V = vws + lv.voff;
+      a.ldv = lv.h;
+      a.Tm = tws + lv.toff;
+      a.ldt = cfg.tile;
+      a.k = (int32_t)(lv.P == 1 ? std::min<int64_t>(bw, lv.h) : bw);
+      HIPCHK(launch_larfb<T>(cfg.tile, cfg.threads / 64, cfg.inner_block, a, st));
+    }
+  }
+  return SVDV_OK;
+}
+
+template <typename T>
+int run_stage1(T* W, int64_t ldw, int64_t M, int64_t N, const svdv_config& cfg, T* vws, T* tws, hipStream_t st) {
+  const int b = cfg.tile;
+  const View<T> colv{W, 1, ldw};
+  const View<T> rowv{W, ldw, 1};
+  for (int64_t k0 = 0; k0 < N; k0 += b) {
+    const int bw = (int)std::min<int64_t>(b, N - k0);
+    // QR sweep: tile column, rows k0..M-1, update columns k0+bw..N-1
+    int rc = run_panel_step<T>(colv, k0, k0, M - k0, bw, N, cfg, vws, tws, st);
+    if (rc) return rc;
+    // LQ sweep: tile row k0..k0+b-1, columns k0+b..N-1 (QR of the transposed view),
+    // update rows k0+b..M-1 (view columns)
+    const int64_t c1 = k0 + b;
+    if (c1 < N) {
+      rc = run_panel_step<T>(rowv, c1, k0, N - c1, b, M, cfg, vws, tws, st);
+      if (rc) return rc;
+    }
+  }
+  return SVDV_OK;
+}
+
+// ----------------------------------------------------------------------------
+// argument checks shared by the entry points
+// ----------------------------------------------------------------------------
+
+int check_matrix_args(const void* A, int64_t m, int64_t n, int64_t lda, int dtype) {
+  if (dtype != SVDV_F32 && dtype != SVDV_F64) return fail(SVDV_ERR_INVALID_ARG, "dtype must be SVDV_F32 or SVDV_F64");
+  if (m < 0 || n < 0) return fail(SVDV_ERR_INVALID_ARG, "m and n must be >= 0");
+  if (lda < std::max<int64_t>(1, m)) return fail(SVDV_ERR_INVALID_ARG, "lda must be >= max(1, m)");
+  if (m > 0 && n > 0 && A == nullptr) return fail(SVDV_ERR_INVALID_ARG, "A is NULL");
+  if (m > (int64_t)1 << 20 || n > (int64_t)1 << 20) return fail(SVDV_ERR_UNSUPPORTED, "dimension above 2^20");
+  return SVDV_OK;
+}
+
+template <typename T>
+int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_t st, const svdv_config& cfg,
+                 double* band_out, int64_t ldband, double* d_out, double* e_out) {
+  const int transpose = m < n;
+  const int64_t M = transpose ? n : m, N = transpose ? m : n;
+  const int64_t ldw = (M + 15) / 16 * 16;
+  const int hmax = chunk_qr_hmax<T>(cfg.tile);
+  Layout L = make_layout(M, N, sizeof(T), cfg.tile, hmax, cfg.sweep_width, ldw);
+  char* ws = nullptr;
+  int rc = get_workspace(st, L.total, &ws);
+  if (rc) return rc;
+  T* W = (T*)(ws + L.W);
+  T* vws = (T*)(ws + L.V);
+  T* tws = (T*)(ws + L.T);
+  double* Bs = (double*)(ws + L.Bs);
+  int* progress = (int*)(ws + L.progress);
+  int* err = (int*)(ws + L.err);
+  unsigned long long* amax = (unsigned long long*)(ws + L.amax);
+  int* expo = (int*)(ws + L.exp);
+  double* d = d_out ? d_out : (double*)(ws + L.d);
+  double* e = e_out ? e_out : (double*)(ws + L.e);
+  double* work = (double*)(ws + L.work);
+
+  HIPCHK(launch_stage_in<T>(A, m, n, lda, transpose, W, ldw, amax, expo, st));
+  rc = run_stage1<T>(W, ldw, M, N, cfg, vws, tws, st);
+  if (rc) return rc;
+  if (band_out) {
+    HIPCHK(launch_band_extract<T>(W, ldw, N, cfg.tile, band_out, ldband, expo, st));
+    return SVDV_OK;
+  }
+  HIPCHK(launch_band_pack<T>(W, ldw, N, cfg.tile, Bs, 3 * cfg.tile, expo, 0, st));
+  ChaseArgs ca;
+  ca.Bs = Bs;
+  ca.ldb = 3 * cfg.tile;
+  ca.n = N;
+  ca.b = cfg.tile;
+  ca.W = cfg.sweep_width;
+  ca.ngroups = (int32_t)std::max<int64_t>(1, (N - 1 + cfg.sweep_width - 1) / cfg.sweep_width);
+  ca.progress = progress;
+  ca.err = err;
+  ca.d = d;
+  ca.e = e;
+  int grid = std::min<int>(ca.ngroups, chase_max_groups_resident(cfg.tile, cfg.sweep_width));
+  if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
+  HIPCHK(launch_chase(ca, grid, st));
+  if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 16, st));
+  return SVDV_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* svdv_status_string(int status) {
+  switch (status) {
+    case SVDV_OK: return "SVDV_OK";
+    case SVDV_ERR_INVALID_ARG: return "SVDV_ERR_INVALID_ARG";
+    case SVDV_ERR_UNSUPPORTED: return "SVDV_ERR_UNSUPPORTED";
+    case SVDV_ERR_NO_MEMORY: return "SVDV_ERR_NO_MEMORY";
+    case SVDV_ERR_HIP: return "SVDV_ERR_HIP";
+  }
+  return "unknown svdv status";
+}
+
+const char* svdv_last_error(void) { return g_last_error.c_str(); }
+
+int svdv_default_config(int64_t m, int64_t n, int32_t dtype, svdv_config* out) {
+  if (!out) return fail(SVDV_ERR_INVALID_ARG, "out is NULL");
+  if (dtype != SVDV_F32 && dtype != SVDV_F64) return fail(SVDV_ERR_INVALID_ARG, "dtype must be SVDV_F32 or SVDV_F64");
+  *out = default_config(m, n, dtype);
+  return SVDV_OK;
+}
+
+int svdv_check_config(int64_t m, int64_t n, int32_t dtype, const svdv_config* cfg) {
+  if (!cfg) return fail(SVDV_ERR_INVALID_ARG, "cfg is NULL");
+  return check_config_impl(m, n, dtype, *cfg);
+}
+
+int svd_values_ex(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream,
+                  const svdv_config* cfg) {
+  int rc = check_matrix_args(A, m, n, lda, dtype);
+  if (rc) return rc;
+  const int64_t k = std::min(m, n);
+  if (k == 0) return SVDV_OK;
+  if (!S) return fail(SVDV_ERR_INVALID_ARG, "S is NULL");
+  svdv_config c = cfg ? *cfg : default_config(m, n, dtype);
+  rc = check_config_impl(m, n, dtype, c);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SVDV_F32)
+    return svd_values_t<float>((const float*)A, m, n, lda, (float*)S, st, c, nullptr, 0, nullptr, nullptr);
+  return svd_values_t<double>((const double*)A, m, n, lda, (double*)S, st, c, nullptr, 0, nullptr, nullptr);
+}
+
+int svd_values(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream) {
+  return svd_values_ex(A, m, n, lda, dtype, S, stream, nullptr);
+}
+
+int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, double* band, int64_t ldband,
+                    void* stream, const svdv_config* cfg) {
+  int rc = check_matrix_args(A, m, n, lda, dtype);
+  if (rc) return rc;
+  const int64_t k = std::min(m, n);
+  if (k == 0) return SVDV_OK;
+  svdv_config c = cfg ? *cfg : default_config(m, n, dtype);
+  rc = check_config_impl(m, n, dtype, c);
+  if (rc) return rc;
+  if (!band) return fail(SVDV_ERR_INVALID_ARG, "band is NULL");
+  if (ldband < c.tile + 1) return fail(SVDV_ERR_INVALID_ARG, "ldband must be >= tile + 1");
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SVDV_F32)
+    return svd_values_t<float>((const float*)A, m, n, lda, nullptr, st, c, band, ldband, nullptr, nullptr);
+  return svd_values_t<double>((const double*)A, m, n, lda, nullptr, st, c, band, ldband, nullptr, nullptr);
+}
+
+int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, double* d, double* e, void* stream,
+                      const svdv_config* cfg) {
+  if (n < 0) return fail(SVDV_ERR_INVALID_ARG, "n must be >= 0");
+  if (n == 0) return SVDV_OK;
+  if (!band || !d || (n > 1 && !e)) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  if (!(b == 16 || b == 32 || b == 64 || b == 128)) return fail(SVDV_ERR_UNSUPPORTED, "b must be 16, 32, 64 or 128");
+  if (ldband < b + 1) return fail(SVDV_ERR_INVALID_ARG, "ldband must be >= b + 1");
+  svdv_config c = cfg ? *cfg : default_config(n, n, SVDV_F64);
+  c.tile = (int32_t)b;
+  if (c.sweep_width < 1 || c.sweep_width > 8) return fail(SVDV_ERR_UNSUPPORTED, "sweep_width must be in 1..8");
+  if (chase_lds_bytes((int)b, c.sweep_width) > 160 * 1024 - 1024)
+    return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase LDS exceeds 160 KiB for this b and sweep width");
+  hipStream_t st = (hipStream_t)stream;
+  Layout L = make_layout(n, n, 8, (int)b, 256, c.sweep_width, n);
+  char* ws = nullptr;
+  int rc = get_workspace(st, L.total, &ws);
+  if (rc) return rc;
+  double* Bs = (double*)(ws + L.Bs);
+  HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
+  ChaseArgs ca;
+  ca.Bs = Bs;
+  ca.ldb = 3 * b;
+  ca.n = n;
+  ca.b = (int32_t)b;
+  ca.W = c.sweep_width;
+  ca.ngroups = (int32_t)std::max<int64_t>(1, (n - 1 + c.sweep_width - 1) / c.sweep_width);
+  ca.progress = (int*)(ws + L.progress);
+  ca.err = (int*)(ws + L.err);
+  ca.d = d;
+  ca.e = e ? e : (double*)(ws + L.e);
+  int grid = std::min<int>(ca.ngroups, chase_max_groups_resident((int)b, c.sweep_width));
+  if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
+  HIPCHK(launch_chase(ca, grid, st));
+  return SVDV_OK;
+}
+
+int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_dtype, void* S, void* stream) {
+  if (n < 0) return fail(SVDV_ERR_INVALID_ARG, "n must be >= 0");
+  if (out_dtype != SVDV_F32 && out_dtype != SVDV_F64) return fail(SVDV_ERR_INVALID_ARG, "bad out_dtype");
+  if (n == 0) return SVDV_OK;
+  if (!d || !S || (n > 1 && !e)) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  Layout L = make_layout(n, n, 8, 16, 256, 1, n);
+  char* ws = nullptr;
+  int rc = get_workspace(st, L.total, &ws);
+  if (rc) return rc;
+  int* expo = (int*)(ws + L.exp);
+  double* work = (double*)(ws + L.work);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, expo, 0, (int64_t)1);
+  const double* ee = e ? e : d;  // n == 1: e is never read
+  if (out_dtype == SVDV_F32) HIPCHK(launch_bisect<float>(d, ee, n, (float*)S, work, expo, 16, st));
+  else HIPCHK(launch_bisect<double>(d, ee, n, (double*)S, work, expo, 16, st));
+  return SVDV_OK;
+}
+
+int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void* C, int64_t ldc, int64_t h, int64_t w,
+                  int64_t k, int32_t dtype, int32_t side, void* stream, const svdv_config* cfg) {
+  if (dtype != SVDV_F32 && dtype != SVDV_F64) return fail(SVDV_ERR_INVALID_ARG, "bad dtype");
+  if (h < 0 || w < 0 || k < 0) return fail(SVDV_ERR_INVALID_ARG, "negative size");
+  if (side != 0 && side != 1) return fail(SVDV_ERR_INVALID_ARG, "side must be 0 (left) or 1 (right)");
+  if (h == 0 || w == 0 || k == 0) return SVDV_OK;
+  if (!V || !Tm || !C) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  const int64_t vrows = side == 0 ? h : w;
+  if (ldc < h || ldv < vrows || ldt < k) return fail(SVDV_ERR_INVALID_ARG, "leading dimension too small");
+  if (k > vrows) return fail(SVDV_ERR_INVALID_ARG, "k exceeds the reflector length");
+  svdv_config c = cfg ? *cfg : default_config(h, w, dtype);
+  int rc = check_config_impl(h, w, dtype, c);
+  if (rc) return rc;
+  if (k > c.tile) return fail(SVDV_ERR_UNSUPPORTED, "k exceeds cfg->tile");
+  hipStream_t st = (hipStream_t)stream;
+  auto run = [&](auto* Cp, auto* Vp, auto* Tp) -> int {
+    typedef std::remove_pointer_t<decltype(Cp)> T;
+    LarfbArgs<T> a;
+    a.M = side == 0 ? View<T>{Cp, 1, ldc} : View<T>{Cp, ldc, 1};
+    a.rm = RowMap{0, 0, 0, 0};
+    a.h = vrows;
+    a.chunk_rows = vrows;
+    a.P = 1;
+    a.col0 = 0;
+    a.col1 = side == 0 ? w : h;
+    a.V = Vp;
+    a.ldv = ldv;
+    a.Tm = Tp;
+    a.ldt = ldt;
+    a.k = (int32_t)k;
+    HIPCHK(launch_larfb<T>(c.tile, c.threads / 64, c.inner_block, a, st));
+    return SVDV_OK;
+  };
+  if (dtype == SVDV_F32) return run((float*)C, (const float*)V, (const float*)Tm);
+  return run((double*)C, (const double*)V, (const double*)Tm);
+}
+
+int svd_values_batched(const void* const* A_array, const int64_t* m, const int64_t* n, const int64_t* lda, int64_t batch,
+                       int32_t dtype, void* S, const int64_t* S_offset, void* stream, const svdv_config* cfg) {
+  if (batch < 0) return fail(SVDV_ERR_INVALID_ARG, "batch must be >= 0");
+  if (batch == 0) return SVDV_OK;
+  if (!A_array || !m || !n || !lda || !S_offset || !S) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  for (int64_t i = 0; i < batch; ++i) {
+    int rc = check_matrix_args(A_array[i], m[i], n[i], lda[i], dtype);
+    if (rc) return rc;
+  }
+  const int es = elem_size(dtype);
+  for (int64_t i = 0; i < batch; ++i) {
+    int rc = svd_values_ex(A_array[i], m[i], n[i], lda[i], dtype, (char*)S + S_offset[i] * es, stream, cfg);
+    if (rc) return rc;
+  }
+  return SVDV_OK;
+}
+
+int svdv_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws) {
+    if (kv.second.ptr) {
+      hipSetDevice(kv.first.first);
+      hipStreamSynchronize((hipStream_t)kv.first.second);
+      hipFree(kv.second.ptr);
+    }
+  }
+  g_ws.clear();
+  return SVDV_OK;
+}
+
+}  // extern "C"

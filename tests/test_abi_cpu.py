@@ -1,0 +1,72 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every declared symbol,
+and validates arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2608_21227_amd as svdv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "svdv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|const char\*)\s+(\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _header_functions() == sorted(svdv.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = svdv.lib()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = svdv.lib()
+    assert lib.svdv_status_string(0) == b"SVDV_OK"
+    assert lib.svdv_status_string(-2) == b"SVDV_ERR_UNSUPPORTED"
+
+
+def test_argument_validation_happens_before_any_gpu_call():
+    lib = svdv.lib()
+    cfg = svdv.Config()
+    dummy = ctypes.c_void_p(0x1000)
+    # negative size, lda too small, bad dtype, NULL A with nonzero size
+    assert lib.svd_values_ex(dummy, -1, 4, 4, 0, dummy, None, ctypes.byref(cfg._c())) == -1
+    assert lib.svd_values_ex(dummy, 8, 4, 4, 0, dummy, None, ctypes.byref(cfg._c())) == -1
+    assert lib.svd_values_ex(dummy, 4, 4, 4, 7, dummy, None, ctypes.byref(cfg._c())) == -1
+    assert lib.svd_values_ex(None, 4, 4, 4, 0, dummy, None, ctypes.byref(cfg._c())) == -1
+    assert b"lda" in lib.svdv_last_error() or b"NULL" in lib.svdv_last_error()
+    # empty matrices succeed and touch nothing
+    assert lib.svd_values_ex(None, 0, 5, 1, 0, None, None, None) == 0
+    assert lib.svd_values_ex(None, 5, 0, 5, 1, None, None, None) == 0
+    # unsupported configurations are reported as such (the tuner's skip signal)
+    bad = svdv.Config(tile=48)
+    assert lib.svd_values_ex(dummy, 4, 4, 4, 0, dummy, None, ctypes.byref(bad._c())) == -2
+    assert lib.svdv_stage_bidiag(dummy, 10, 24, 25, dummy, dummy, None, None) == -2
+    assert lib.svdv_apply_qt(dummy, 4, dummy, 4, dummy, 4, 4, 4, 4, 0, 5, None, None) == -1
+
+
+def test_config_space_validity_rules():
+    # float64 tile 128 is not built; oversized register tiles are rejected
+    assert not svdv.check_config(256, 256, "float64", svdv.Config(tile=128))
+    assert svdv.check_config(256, 256, "float32", svdv.Config(tile=128, threads=256, inner_block=1, sweep_width=2))
+    assert not svdv.check_config(256, 256, "float32", svdv.Config(tile=128, threads=1024, inner_block=8))
+    assert svdv.check_config(256, 256, "float64", svdv.Config(tile=16, threads=64, inner_block=8, sweep_width=8))
+    assert not svdv.check_config(256, 256, "float32", svdv.Config(tile=128, sweep_width=8))
+    d = svdv.default_config(4096, 4096, "float32")
+    assert svdv.check_config(4096, 4096, "float32", d)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import importlib
+    monkeypatch.setattr(svdv, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(svdv, "_lib", None)
+    with pytest.raises(RuntimeError):
+        svdv.lib()

@@ -1,0 +1,193 @@
+"""GPU parity: every stage through the C-ABI against the CPU oracle, on seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import banner, gate, sigma_errors, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _svdv():
+    import paper_2608_21227_amd as svdv
+    return svdv
+
+
+# ----------------------------------------------------------------------------- K2 alone
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("h,w,k,tile,threads,ib", [
+    (100, 70, 16, 16, 64, 1), (256, 300, 32, 32, 256, 2), (513, 129, 64, 64, 128, 2), (77, 33, 7, 16, 64, 4),
+    (300, 250, 128, 128, 256, 1)])
+def test_apply_qt_matches_explicit_product(dtype, side, h, w, k, tile, threads, ib):
+    torch = torch_cuda()
+    svdv = _svdv()
+    cfg = svdv.Config(tile=tile, threads=threads, inner_block=ib, sweep_width=1)
+    if not svdv.check_config(h, w, dtype, cfg):
+        pytest.skip("configuration not built for this dtype")
+    rng = np.random.default_rng(h * 7 + w + k + side)
+    vr = h if side == 0 else w
+    V = np.tril(rng.standard_normal((vr, k)), -1)
+    V[np.arange(k), np.arange(k)] = 1.0
+    T = np.triu(rng.standard_normal((k, k)) * 0.3)
+    C = rng.standard_normal((h, w))
+    npdt = np.float32 if dtype == "float32" else np.float64
+    V, T, C = V.astype(npdt), T.astype(npdt), C.astype(npdt)
+    Q = np.eye(vr) - V.astype(np.float64) @ T.astype(np.float64) @ V.astype(np.float64).T
+    want = Q.T @ C.astype(np.float64) if side == 0 else C.astype(np.float64) @ Q
+    banner(f"apply_qt {dtype} side={side} h={h} w={w} k={k} tile={tile} threads={threads} ib={ib}")
+    Vd, Td, Cd = (to_dev(x, torch, fortran=True) for x in (V, T, C))
+    svdv.apply_qt(Vd, Td, Cd, side=side, config=cfg)
+    torch.cuda.synchronize()
+    got = Cd.cpu().numpy().astype(np.float64)
+    scale = np.linalg.norm(want) + np.linalg.norm(C)
+    tol = 1e-13 if dtype == "float64" else 2e-6
+    assert np.max(np.abs(got - want)) <= tol * scale
+
+
+# ----------------------------------------------------------------------------- stage 1
+@pytest.mark.parametrize("n,tile", [(64, 16), (256, 32), (200, 64), (97, 16), (130, 32)])
+def test_stage_band_matches_oracle_up_to_signs(n, tile):
+    torch = torch_cuda()
+    svdv = _svdv()
+    a = workloads.gaussian(n, n, cfg_id=70, dtype="float64")
+    banner(f"stage_band float64 n={n} tile={tile}")
+    band = svdv.stage_band(to_dev(a, torch, fortran=True), config=svdv.Config(tile=tile, threads=256,
+                                                                               inner_block=2, sweep_width=1))
+    torch.cuda.synchronize()
+    band = band.cpu().numpy()
+    ref = oracle.band_reduce(a, tile)
+    full = np.zeros((n, n))
+    for d in range(tile + 1):
+        idx = np.arange(n - d)
+        full[idx, idx + d] = band[idx, d]
+    # uniqueness of the band up to row/column signs (R factors are unique up to signs)
+    assert np.max(np.abs(np.abs(full) - np.abs(ref))) <= 1e-12 * np.linalg.norm(a)
+    assert abs(abs(full[0, 0]) - np.linalg.norm(a[:, 0])) <= 1e-13 * np.linalg.norm(a[:, 0])
+    s = oracle.svd_values(a)
+    assert np.max(np.abs(oracle.svd_values(full) - s)) <= 1e-12 * s[0]
+
+
+def test_stage_band_rectangular_and_float32():
+    torch = torch_cuda()
+    svdv = _svdv()
+    for (m, n, dt) in [(150, 90, "float64"), (90, 150, "float64"), (300, 300, "float32")]:
+        a = workloads.as_dtype(workloads.gaussian(m, n, cfg_id=71, dtype=dt), dt)
+        banner(f"stage_band {dt} m={m} n={n}")
+        band = svdv.stage_band(to_dev(a, torch, fortran=True), config=svdv.Config(tile=32)).cpu().numpy()
+        k = min(m, n)
+        full = np.zeros((k, k))
+        for d in range(33):
+            idx = np.arange(k - d)
+            full[idx, idx + d] = band[idx, d]
+        s = oracle.svd_values(a)
+        tol = 1e-12 if dt == "float64" else 1e-5
+        assert np.max(np.abs(oracle.svd_values(full) - s)) <= tol * s[0]
+
+
+# ----------------------------------------------------------------------------- stage 2
+@pytest.mark.parametrize("n,b", [(50, 16), (129, 16), (200, 32), (150, 64), (300, 128)])
+def test_stage_bidiag_matches_oracle(n, b):
+    torch = torch_cuda()
+    svdv = _svdv()
+    a = workloads.gaussian(n, n, cfg_id=72, dtype="float64")
+    band_dense = oracle.band_reduce(a, b)
+    band = np.zeros((n, b + 1))
+    for d in range(b + 1):
+        idx = np.arange(n - d)
+        band[idx, d] = band_dense[idx, idx + d]
+    d_ref, e_ref = oracle.bulge_chase(band_dense, b)
+    scale = np.linalg.norm(band_dense)
+    results = []
+    for W in (1, 3, 8):
+        cfg = svdv.Config(tile=b, sweep_width=W)
+        if not svdv.check_config(n, n, "float32", cfg):
+            continue
+        banner(f"stage_bidiag n={n} b={b} W={W}")
+        d, e = svdv.stage_bidiag(to_dev(band, torch), b, config=cfg)
+        torch.cuda.synchronize()
+        d, e = d.cpu().numpy(), e.cpu().numpy()
+        assert np.max(np.abs(np.abs(d) - np.abs(d_ref))) <= 1e-12 * scale
+        assert np.max(np.abs(np.abs(e) - np.abs(e_ref))) <= 1e-12 * scale
+        results.append((d, e))
+    for d, e in results[1:]:  # schedule-independent: bitwise equal for every sweep width
+        assert np.array_equal(d, results[0][0]) and np.array_equal(e, results[0][1])
+
+
+# ----------------------------------------------------------------------------- stage 3
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 333, 1000])
+def test_stage_values_matches_oracle(n):
+    torch = torch_cuda()
+    svdv = _svdv()
+    rng = np.random.default_rng(n)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(max(n - 1, 0))
+    banner(f"stage_values n={n}")
+    s = svdv.stage_values(to_dev(d, torch), to_dev(e, torch)).cpu().numpy()
+    ref = oracle.bidiag_values(d, e)
+    assert np.max(np.abs(s - ref)) <= 4 * max(n, 4) * 2.0 ** -53 * ref[0] * 4
+
+
+def test_stage_values_special_cases():
+    torch = torch_cuda()
+    svdv = _svdv()
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal(40)
+    banner("stage_values e=0")
+    s = svdv.stage_values(to_dev(d, torch), to_dev(np.zeros(39), torch)).cpu().numpy()
+    assert np.max(np.abs(s - np.sort(np.abs(d))[::-1])) <= 8 * 2.0 ** -53 * np.max(np.abs(d))
+    s = svdv.stage_values(to_dev(np.ones(10), torch), to_dev(np.zeros(9), torch)).cpu().numpy()
+    assert np.max(np.abs(s - 1.0)) <= 8 * 2.0 ** -53
+
+
+# ----------------------------------------------------------------------------- end to end
+def test_cfg0_known_spectrum_float64():
+    torch = torch_cuda()
+    svdv = _svdv()
+    a = workloads.cfg0_matrix()
+    banner("end-to-end cfg0 256x256 float64 tile 32")
+    s = svdv.svd_values(to_dev(a, torch, fortran=True), config=svdv.Config(tile=32, threads=256, inner_block=1,
+                                                                            sweep_width=1)).cpu().numpy()
+    ref = oracle.svd_values(a)
+    gate("float64", s, ref)
+    assert np.max(np.abs(s - workloads.cfg0_spectrum())) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("m,n,tile", [(300, 300, 16), (300, 300, 32), (257, 257, 64), (1000, 1000, 32),
+                                      (1025, 1025, 16), (400, 250, 32), (250, 400, 32), (1, 1, 16), (7, 1, 16),
+                                      (1, 9, 32), (33, 33, 128)])
+def test_end_to_end_matches_oracle(dtype, m, n, tile):
+    torch = torch_cuda()
+    svdv = _svdv()
+    cfg = svdv.Config(tile=tile, threads=256, inner_block=2, sweep_width=4 if tile < 128 else 2)
+    if not svdv.check_config(m, n, dtype, cfg):
+        pytest.skip("configuration not built for this dtype")
+    a = workloads.as_dtype(workloads.gaussian(m, n, cfg_id=73, dtype=dtype), dtype)
+    banner(f"end-to-end {dtype} m={m} n={n} tile={tile}")
+    s = svdv.svd_values(to_dev(a, torch, fortran=True), config=cfg).cpu().numpy()
+    ref = oracle.svd_values(a)
+    gate(dtype, s, ref)
+
+
+def test_edge_cases_and_invariants():
+    torch = torch_cuda()
+    svdv = _svdv()
+    empty = torch.zeros((0, 5), dtype=torch.float64, device="cuda")
+    assert svdv.svd_values(empty).numel() == 0
+    z = torch.zeros((20, 10), dtype=torch.float32, device="cuda")
+    banner("zero matrix")
+    assert torch.all(svdv.svd_values(z) == 0)
+    a = workloads.gaussian(120, 120, cfg_id=74, dtype="float64")
+    cfg = svdv.Config(tile=16, sweep_width=2)
+    banner("power-of-two scaling")
+    s1 = svdv.svd_values(to_dev(a, torch, fortran=True), config=cfg).cpu().numpy()
+    s2 = svdv.svd_values(to_dev(np.ldexp(a, 37), torch, fortran=True), config=cfg).cpu().numpy()
+    assert np.array_equal(np.ldexp(s1, 37), s2)
+    banner("row-major input (transpose path)")
+    s3 = svdv.svd_values(to_dev(a, torch), config=cfg).cpu().numpy()
+    assert np.max(np.abs(s3 - s1)) <= 1e-13 * s1[0]
+    banner("repeatability")
+    s4 = svdv.svd_values(to_dev(a, torch, fortran=True), config=cfg).cpu().numpy()
+    assert np.array_equal(s1, s4)
