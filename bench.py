@@ -1,0 +1,177 @@
+"""Headline benchmark: singular values of a dense n=4096 float32 matrix (i.i.d. N(0,1)) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096] [--dtype float32] [--no-cpu]
+
+A step is one call of the whole hot path (input staging, stage 1 band
+reduction, band packing, stage 2 bulge chase, stage 3 bisection) on the same
+device-resident input.  The metric is GFLOP/s on the nominal 4n^3/3 basis for
+the tuned configuration; the median and plain (untuned default)
+configurations of the auto-tuner's space are timed the same way beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_2608_21227_amd as svdv  # noqa: E402
+import workloads  # noqa: E402
+from paper_2608_21227_amd import tuner  # noqa: E402
+
+PEAKS = {"hbm_GBs": 8000.0, "fp32_TF": 157.3, "fp64_TF": 78.6, "fp64_vec_TF": 78.6}
+
+
+def chase_flops(n: int, b: int) -> float:
+    """Algorithmic flops of one bulge-chase launch: per task 4 flops per element of the right
+    (rows p+1..c+L-1 x L) and left (L x columns c+1..c+L+b-1) reflector applications."""
+    total = 0.0
+    for s in range(n - 1):
+        p, c = s, s + 1
+        while c < n:
+            L = min(b, n - c)
+            rend = min(c + L, n)
+            cend = min(c + L + b, n)
+            total += 4.0 * (rend - p - 1) * L + 4.0 * L * (cend - c - 1)
+            p, c = c, c + b
+    return total
+
+
+def time_config(a, cfg, steps: int, warmup: int, torch):
+    for _ in range(warmup):
+        svdv.svd_values(a, config=cfg)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        s = svdv.svd_values(a, config=cfg)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall, s
+
+
+def stage_breakdown(a, cfg, reps: int, torch):
+    svdv.set_timing(True)
+    acc = {}
+    for _ in range(reps):
+        svdv.svd_values(a, config=cfg)
+        t = svdv.last_timing()
+        for k, v in t.items():
+            acc.setdefault(k, []).append(v)
+    svdv.set_timing(False)
+    torch.cuda.synchronize()
+    return {k: float(np.median(v)) for k, v in acc.items()}
+
+
+def cpu_baseline(a_np: np.ndarray, n: int, sweeps_total: int):
+    import oracle
+    threads = os.cpu_count() or 1
+    secs, done = oracle.time_sweeps(a_np, 1, threads=threads)
+    est = secs * sweeps_total
+    gflops = (4.0 / 3.0) * n ** 3 / est / 1e9
+    return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 of the {sweeps_total} Jacobi sweeps the oracle needs on this n={n} matrix "
+                      f"({secs:.1f} s, float64, OpenMP), extrapolated x{sweeps_total}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-tuned", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    n, dtype = args.n, args.dtype
+    print(f"[bench] generating n={n} {dtype} input", file=sys.stderr, flush=True)
+    a_np = workloads.cfg1_matrix(n, dtype)
+    a = torch.from_numpy(np.ascontiguousarray(a_np.T)).t().cuda()  # column-major on device
+    nominal = (4.0 / 3.0) * n ** 3
+
+    table = tuner.load_table()
+    tuned = tuner.lookup(table, n, dtype) or svdv.default_config(n, n, dtype)
+    plain = tuner.PLAIN
+    median = tuner.lookup_median(table, n, dtype)
+    res = {}
+    order = [("tuned", tuned)] + ([] if args.only_tuned else [("plain", plain)] + ([("median", median)] if median else []))
+    for name, cfg in order:
+        print(f"[bench] timing {name} {cfg}", file=sys.stderr, flush=True)
+        ms, wall, s = time_config(a, cfg, args.steps, args.warmup, torch)
+        res[name] = {"config": cfg.as_dict(), "ms": ms, "gflops": nominal / (ms * 1e-3) / 1e9, "wall_s": wall}
+        if name == "tuned":
+            s_tuned = s.cpu().numpy().astype(np.float64)
+    print("[bench] stage breakdown", file=sys.stderr, flush=True)
+    stages = stage_breakdown(a, tuned, 3, torch)
+
+    # parity spot check against the stored oracle values (full size)
+    gold = os.path.join(ROOT, "tests", "golden", f"cfg1_n{n}_{dtype}.npy")
+    parity = None
+    if os.path.exists(gold):
+        ref = np.load(gold)
+        diff = np.abs(s_tuned - ref)
+        parity = {"normwise": float(diff.max() / ref[0]), "max_rel": float(np.max(diff / ref))}
+
+    # roofline of the dominant kernel: the bulge chase (one launch per call)
+    b = tuned.tile
+    fl = chase_flops(n, b)
+    t_chase = stages.get("chase", float("nan")) * 1e-3
+    achieved = fl / t_chase / 1e12
+    t_stage1 = stages.get("stage1", float("nan")) * 1e-3
+    s1_flops = 8.0 / 3.0 * n ** 3
+    roofline = {"bound": "alu", "kernel": "k_chase (stage 2 bulge chase, float64)", "achieved": round(achieved, 5),
+                "peak": PEAKS["fp64_vec_TF"], "unit": "TFLOP/s", "frac": round(achieved / PEAKS["fp64_vec_TF"], 6),
+                "traffic": None, "flops_per_launch": fl}
+
+    tuned_ms = res["tuned"]["ms"]
+    out = {
+        "metric": "SVD-values GFLOP/s (4n³/3 basis) tuned vs median config, n=4096 FP32, 1 MI355X",
+        "value": round(res["tuned"]["gflops"], 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tuned_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == "float32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dense {n}x{n} {dtype} i.i.d. N(0,1) singular values (two-stage: band, bulge chase, bisection)",
+                   "n": n, "tuned": res["tuned"]["config"]},
+        "median_gflops": round(res["median"]["gflops"], 3) if "median" in res else None,
+        "plain_gflops": round(res["plain"]["gflops"], 3) if "plain" in res else None,
+        "tuned_over_median": round(res["median"]["ms"] / tuned_ms, 3) if "median" in res else None,
+        "tuned_over_plain": round(res["plain"]["ms"] / tuned_ms, 3) if "plain" in res else None,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "stage1_roofline_frac": round(max(s1_flops / (PEAKS["fp32_TF" if dtype == "float32" else "fp64_TF"] * 1e12),
+                                          4 * (4 if dtype == "float32" else 8) * n ** 3 / (3 * b) / (PEAKS["hbm_GBs"] * 1e9))
+                                      / t_stage1, 5),
+        "roofline": roofline,
+        "parity_vs_oracle": parity,
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a_np, n, 18)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

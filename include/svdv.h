@@ -153,6 +153,17 @@ int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_d
 int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* C, int64_t ldc, int64_t h, int64_t w,
                   int64_t k, int32_t dtype, int32_t side, void* stream, const svdv_config* cfg);
 
+/*
+ * Stage timing (instrumentation).  svdv_timing(1) makes every later call on the
+ * calling thread record HIP events on its stream around: [0] input staging,
+ * [1] stage 1 (all panel and update launches), [2] band packing, [3] the
+ * bulge-chase kernel, [4] the bisection kernels.  svdv_last_timing waits for
+ * the last call's events and writes up to n elapsed times in milliseconds
+ * (HOST array) followed by [5] the whole call; returns the count written.
+ */
+int svdv_timing(int enable);
+int svdv_last_timing(double* ms, int n);
+
 /* Text for a status code (static string). */
 const char* svdv_status_string(int status);
 /* Detail of the last error on the calling thread (thread-local, static lifetime). */

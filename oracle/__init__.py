@@ -275,3 +275,20 @@ def golub_kahan(a) -> tuple[np.ndarray, np.ndarray]:
             w[j, j + 1] = beta
             w[j, j + 2:] = 0.0
     return np.diag(w[:n, :n]).copy(), np.diag(w[:n, :n], 1).copy()
+
+
+def time_sweeps(a, sweeps: int, threads: int = 0) -> tuple[float, int]:
+    """Wall time of the first ``sweeps`` Jacobi sweeps on ``a`` (bounded oracle timing sample).
+
+    Returns (seconds, sweeps actually run).  Used only to time the oracle on a
+    bounded sample; the values it would return are not used."""
+    import time
+    a64 = np.asfortranarray(np.asarray(a).astype(np.float64))
+    m, n = a64.shape
+    out = np.zeros(min(m, n), dtype=np.float64)
+    done = ctypes.c_int(0)
+    off = ctypes.c_double(0.0)
+    t0 = time.perf_counter()
+    _load().oracle_svd_values(a64.ctypes.data, m, n, max(1, m), out.ctypes.data, sweeps, threads,
+                              ctypes.byref(done), ctypes.byref(off))
+    return time.perf_counter() - t0, done.value

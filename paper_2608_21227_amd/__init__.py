@@ -22,7 +22,7 @@ STATUS = {0: "SVDV_OK", -1: "SVDV_ERR_INVALID_ARG", -2: "SVDV_ERR_UNSUPPORTED", 
 # Every symbol include/svdv.h declares (checked by the CPU test-suite).
 EXPORTS = ["svd_values", "svd_values_ex", "svd_values_batched", "svdv_default_config", "svdv_check_config",
            "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
-           "svdv_last_error", "svdv_release"]
+           "svdv_last_error", "svdv_release", "svdv_timing", "svdv_last_timing"]
 
 
 class SvdvError(RuntimeError):
@@ -78,6 +78,8 @@ def lib():
             "svdv_stage_values": [vp, vp, i64, i32, vp, vp],
             "svdv_apply_qt": [vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp, cfgp],
             "svdv_release": [],
+            "svdv_timing": [ctypes.c_int],
+            "svdv_last_timing": [ctypes.POINTER(ctypes.c_double), ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -251,6 +253,23 @@ def apply_qt(V, T, C, side: int = 0, config=None):
                                T.stride(1), ctypes.c_void_p(C.data_ptr()), C.stride(1), h, w, k, dt, side,
                                _stream(C.device), _cfg_ptr(config)))
     return C
+
+
+STAGES = ["stage_in", "stage1", "band_pack", "chase", "bisect", "total"]
+
+
+def set_timing(enable: bool):
+    """Record per-stage HIP events in later calls on this thread (instrumentation)."""
+    _check(lib().svdv_timing(1 if enable else 0))
+
+
+def last_timing() -> dict:
+    """Per-stage milliseconds of the last timed call (waits for its events)."""
+    buf = (ctypes.c_double * 6)()
+    k = lib().svdv_last_timing(buf, 6)
+    if k < 0:
+        _check(k)
+    return {name: buf[i] for i, name in enumerate(STAGES[:k])}
 
 
 def release():

@@ -34,15 +34,43 @@ struct RowMap {
   }
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+// Wave-wide sums with DPP lane moves (quad permutes, row shifts and the row
+// broadcasts of wave64), the total collected in lane 63 and returned to every
+// lane through a scalar register, so all lanes see bitwise the same value.
+// Must be called with the whole wave active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_f<0xb1>(v);   // quad_perm 1,0,3,2
+  v += dpp_f<0x4e>(v);   // quad_perm 2,3,0,1
+  v += dpp_f<0x114>(v);  // row_shr:4
+  v += dpp_f<0x118>(v);  // row_shr:8
+  v += dpp_f<0x142>(v);  // row_bcast:15
+  v += dpp_f<0x143>(v);  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x114>(v);
+  v += dpp_d<0x118>(v);
+  v += dpp_d<0x142>(v);
+  v += dpp_d<0x143>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // MFMA 16x16x4: D[16x16] += A[16x4] * B[4x16].
@@ -54,6 +82,12 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// Row of the 16x16 MFMA result held in register i of lane-group g (g = lane / 16):
+// float: 4g + i, double: 4i + g (measured on gfx950).
+template <typename T> __device__ __forceinline__ int acc_row(int g, int i);
+template <> __device__ __forceinline__ int acc_row<float>(int g, int i) { return 4 * g + i; }
+template <> __device__ __forceinline__ int acc_row<double>(int g, int i) { return 4 * i + g; }
 
 template <typename T> struct Acc;
 template <> struct Acc<float> { typedef f32x4 type; };

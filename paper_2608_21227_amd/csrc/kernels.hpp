@@ -40,15 +40,24 @@ struct LarfbArgs {
 };
 
 // Register estimate (32-bit registers per lane) of the trailing-update kernel:
-// Z and Z' accumulators (KT x IB tiles), the C tile (IB), the V operand (KT).
+// the Z accumulators / Z' operands (KT x IB tiles), two slabs of C (IB) and V
+// (KT) in flight, the C accumulator of pass 2.
+// (calibrated against the compiler's resource report so that no valid
+// configuration spills registers to scratch)
 template <typename T>
 constexpr int larfb_regs(int KT, int IB) {
-  return (2 * KT * IB * 4 + IB * 4 + KT * 4 + 20) * (int)(sizeof(T) / 4);
+  return (2 * KT * IB * 4 + 3 * IB * 4 + 2 * KT * 4 + 48) * (int)(sizeof(T) / 4);
 }
-constexpr int larfb_budget(int NW) { return NW >= 16 ? 128 : 256; }
+constexpr int larfb_budget(int NW) { return NW >= 16 ? 96 : (NW >= 8 ? 176 : 256); }
+// LDS: NW partial Z tiles plus Z' (each KT*16 x IB*16).
+template <typename T>
+constexpr size_t larfb_lds(int KT, int IB, int NW) {
+  return (size_t)(NW + 1) * (KT * 16) * (IB * 16) * sizeof(T);
+}
 template <typename T>
 constexpr bool larfb_valid(int KT, int IB, int NW) {
-  return larfb_regs<T>(KT, IB) <= larfb_budget(NW) && !(sizeof(T) == 8 && KT > 4);
+  return larfb_regs<T>(KT, IB) <= larfb_budget(NW) && !(sizeof(T) == 8 && KT > 4) &&
+         larfb_lds<T>(KT, IB, NW) <= 128 * 1024;
 }
 
 // Fill kernels (used instead of hipMemsetAsync so that every step can be captured in a graph).

@@ -16,6 +16,7 @@
 // products on the MFMA units.  Each wave owns IB 16-column tiles and walks the
 // chunk's rows twice (V^T C, then the rank-k update); nothing is shared between
 // waves, so no LDS and no barriers are needed.
+#include <algorithm>
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -53,7 +54,13 @@ __global__ void k_absmax(const T* __restrict__ A, int64_t m, int64_t n, int64_t 
     unsigned long long o = __shfl_xor(b, off, kWave);
     b = o > b ? o : b;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(out, b);
+  __shared__ unsigned long long wmax[16];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = wmax[w] > b ? wmax[w] : b;
+    atomicMax(out, b);
+  }
 }
 
 // exponent e with max*2^-e in [0.5, 1); 0 if max is zero or not finite
@@ -270,122 +277,6 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
 // a3/a5: trailing update  C <- (I - V T V^T)^T C  on MFMA
 // ---------------------------------------------------------------------------
 
-// Row of the 16x16 MFMA result held in register i of lane-group g (g = lane / 16):
-// float: 4g + i, double: 4i + g (measured on gfx950).
-template <typename T> __device__ __forceinline__ int acc_row(int g, int i);
-template <> __device__ __forceinline__ int acc_row<float>(int g, int i) { return 4 * g + i; }
-template <> __device__ __forceinline__ int acc_row<double>(int g, int i) { return 4 * i + g; }
-
-template <typename T, int KT, int IB, int NW>
-__global__ void __launch_bounds__(NW * 64) k_larfb(LarfbArgs<T> a) {
-  typedef typename Acc<T>::type AccT;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int NWv = NW;
-  const int g = lane >> 4, nl = lane & 15;
-  const int c = blockIdx.y;
-  const int64_t row0 = (int64_t)c * a.chunk_rows;
-  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
-  const int k = a.k;
-  const int64_t colbase = a.col0 + ((int64_t)blockIdx.x * NWv + wv) * (IB * 16);
-  if (colbase >= a.col1) return;  // whole wave idle (no barriers in this kernel)
-  const T* V = a.V + row0;
-  const T* Tm = a.Tm + (int64_t)c * a.ldt * a.ldt;
-
-  AccT Z[KT][IB];
-#pragma unroll
-  for (int mt = 0; mt < KT; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
-
-  const int nslab = (Hc + 15) >> 4;
-  // ---- pass 1: Z = V^T C ----
-  for (int s = 0; s < nslab; ++s) {
-    T cb[IB][4], av[KT][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = s * 16 + acc_row<T>(g, i);
-      const bool rok = q < Hc;
-      const int64_t gr = rok ? a.rm.row(c, q) : 0;
-#pragma unroll
-      for (int nt = 0; nt < IB; ++nt) {
-        const int64_t col = colbase + nt * 16 + nl;
-        cb[nt][i] = (rok && col < a.col1) ? a.M.at(gr, col) : T(0);
-      }
-#pragma unroll
-      for (int mt = 0; mt < KT; ++mt) {
-        const int r = mt * 16 + nl;
-        av[mt][i] = (rok && r < k) ? V[q + (int64_t)r * a.ldv] : T(0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int mt = 0; mt < KT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(av[mt][i], cb[nt][i], Z[mt][nt]);
-  }
-
-  // ---- Z' = T^T Z ----
-  AccT Zp[KT][IB];
-#pragma unroll
-  for (int ot = 0; ot < KT; ++ot)
-#pragma unroll
-    for (int nt = 0; nt < IB; ++nt) Zp[ot][nt] = AccT{0, 0, 0, 0};
-#pragma unroll
-  for (int ot = 0; ot < KT; ++ot) {
-#pragma unroll
-    for (int mt = 0; mt < KT; ++mt) {
-      if (mt > ot) continue;  // T upper triangular: T[in][out] = 0 for in > out
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rin = mt * 16 + acc_row<T>(g, i), rout = ot * 16 + nl;
-        const T tv = (rin < k && rout < k) ? Tm[rin + (int64_t)rout * a.ldt] : T(0);
-#pragma unroll
-        for (int nt = 0; nt < IB; ++nt) Zp[ot][nt] = mfma16(tv, Z[mt][nt][i], Zp[ot][nt]);
-      }
-    }
-  }
-
-  // ---- pass 2: C -= V Z' ----
-  for (int s = 0; s < nslab; ++s) {
-    AccT cd[IB];
-    int64_t grow[4];
-    bool rok[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = s * 16 + acc_row<T>(g, i);
-      rok[i] = q < Hc;
-      grow[i] = rok[i] ? a.rm.row(c, q) : 0;
-#pragma unroll
-      for (int nt = 0; nt < IB; ++nt) {
-        const int64_t col = colbase + nt * 16 + nl;
-        cd[nt][i] = (rok[i] && col < a.col1) ? a.M.at(grow[i], col) : T(0);
-      }
-    }
-    const int qa = s * 16 + nl;  // A-operand row (V row)
-    const bool aok = qa < Hc;
-#pragma unroll
-    for (int ot = 0; ot < KT; ++ot) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = ot * 16 + acc_row<T>(g, i);
-        const T vv = (aok && r < k) ? -V[qa + (int64_t)r * a.ldv] : T(0);
-#pragma unroll
-        for (int nt = 0; nt < IB; ++nt) cd[nt] = mfma16(vv, Zp[ot][nt][i], cd[nt]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!rok[i]) continue;
-#pragma unroll
-      for (int nt = 0; nt < IB; ++nt) {
-        const int64_t col = colbase + nt * 16 + nl;
-        if (col < a.col1) a.M.at(grow[i], col) = cd[nt][i];
-      }
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // a6: band pack -- W (dtype T, column-major) -> chase storage (float64, row-major,
 // row i holds columns i-(b-1) .. i+2b-1 at offsets 0 .. 3b-2; width ldb)
@@ -446,7 +337,7 @@ template <typename T>
 hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int transpose, T* W, int64_t ldw,
                            unsigned long long* amax, int* exp_out, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, amax, 1ull * 0, (int64_t)1);
-  hipLaunchKernelGGL(k_absmax<T>, dim3(grid_for(m * n, 256)), dim3(256), 0, st, A, m, n, lda, amax);
+  hipLaunchKernelGGL(k_absmax<T>, dim3(std::min(grid_for(m * n, 256), 1024)), dim3(256), 0, st, A, m, n, lda, amax);
   hipLaunchKernelGGL(k_copy_scale<T>, dim3(grid_for(m * n, 256)), dim3(256), 0, st, A, m, n, lda, transpose, W, ldw,
                      amax, exp_out);
   return hipGetLastError();
@@ -499,54 +390,6 @@ hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-template <typename T, int KT, int IB, int NW>
-static hipError_t launch_larfb_nw(const LarfbArgs<T>& a, hipStream_t st) {
-  if constexpr (larfb_valid<T>(KT, IB, NW)) {
-    const int64_t ncols = a.col1 - a.col0;
-    const int64_t per_block = (int64_t)NW * IB * 16;
-    const dim3 grid((unsigned)((ncols + per_block - 1) / per_block), (unsigned)a.P);
-    hipLaunchKernelGGL((k_larfb<T, KT, IB, NW>), grid, dim3(NW * 64), 0, st, a);
-    return hipGetLastError();
-  } else {
-    return hipErrorInvalidConfiguration;
-  }
-}
-
-template <typename T, int KT, int IB>
-static hipError_t launch_larfb_ib(int nw, const LarfbArgs<T>& a, hipStream_t st) {
-  switch (nw) {
-    case 1: return launch_larfb_nw<T, KT, IB, 1>(a, st);
-    case 2: return launch_larfb_nw<T, KT, IB, 2>(a, st);
-    case 4: return launch_larfb_nw<T, KT, IB, 4>(a, st);
-    case 8: return launch_larfb_nw<T, KT, IB, 8>(a, st);
-    case 16: return launch_larfb_nw<T, KT, IB, 16>(a, st);
-  }
-  return hipErrorInvalidConfiguration;
-}
-
-template <typename T, int KT>
-static hipError_t launch_larfb_kt(int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
-  switch (ib) {
-    case 1: return launch_larfb_ib<T, KT, 1>(nw, a, st);
-    case 2: return launch_larfb_ib<T, KT, 2>(nw, a, st);
-    case 4: return launch_larfb_ib<T, KT, 4>(nw, a, st);
-    case 8: return launch_larfb_ib<T, KT, 8>(nw, a, st);
-  }
-  return hipErrorInvalidConfiguration;
-}
-
-template <typename T>
-hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
-  if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
-  switch (tile) {
-    case 16: return launch_larfb_kt<T, 1>(nw, ib, a, st);
-    case 32: return launch_larfb_kt<T, 2>(nw, ib, a, st);
-    case 64: return launch_larfb_kt<T, 4>(nw, ib, a, st);
-    case 128: return launch_larfb_kt<T, 8>(nw, ib, a, st);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T>
 hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,
                             int unscale, hipStream_t st) {
@@ -572,7 +415,6 @@ hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, d
   template hipError_t launch_stage_in<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t, unsigned long long*, \
                                          int*, hipStream_t);                                                      \
   template hipError_t launch_chunk_qr<T>(int, const ChunkQRArgs<T>&, hipStream_t);                               \
-  template hipError_t launch_larfb<T>(int, int, int, const LarfbArgs<T>&, hipStream_t);                          \
   template hipError_t launch_band_pack<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*, int,     \
                                           hipStream_t);                                                           \
   template hipError_t launch_band_extract<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*,       \

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -18,6 +19,19 @@ using namespace svdv;
 namespace {
 
 thread_local std::string g_last_error;
+
+// Optional per-stage event timing (see svdv_timing in the header).
+struct Timing {
+  bool enabled = false;
+  bool valid = false;
+  hipEvent_t ev[7] = {};
+  void mark(int i, hipStream_t st) {
+    if (!enabled) return;
+    if (!ev[i]) hipEventCreate(&ev[i]);
+    hipEventRecord(ev[i], st);
+  }
+};
+thread_local Timing g_timing;
 
 int fail(int status, const std::string& msg) {
   g_last_error = msg;
@@ -188,6 +202,17 @@ int get_workspace(void* stream, size_t bytes, char** out) {
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
+// Persistent grid of the bulge chase: every workgroup must be resident at once.
+// SVDV_CHASE_GRID (debugging aid) caps it further, e.g. 1 = all groups in one workgroup.
+int chase_grid(int ngroups, int b, int W) {
+  int g = std::min<int>(ngroups, chase_max_groups_resident(b, W));
+  if (const char* env = getenv("SVDV_CHASE_GRID")) {
+    const int cap = atoi(env);
+    if (cap > 0) g = std::min(g, cap);
+  }
+  return g;
+}
+
 struct Layout {
   size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, total;
 };
@@ -319,14 +344,19 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   double* e = e_out ? e_out : (double*)(ws + L.e);
   double* work = (double*)(ws + L.work);
 
+  g_timing.valid = false;
+  g_timing.mark(0, st);
   HIPCHK(launch_stage_in<T>(A, m, n, lda, transpose, W, ldw, amax, expo, st));
+  g_timing.mark(1, st);
   rc = run_stage1<T>(W, ldw, M, N, cfg, vws, tws, st);
   if (rc) return rc;
+  g_timing.mark(2, st);
   if (band_out) {
     HIPCHK(launch_band_extract<T>(W, ldw, N, cfg.tile, band_out, ldband, expo, st));
     return SVDV_OK;
   }
   HIPCHK(launch_band_pack<T>(W, ldw, N, cfg.tile, Bs, 3 * cfg.tile, expo, 0, st));
+  g_timing.mark(3, st);
   ChaseArgs ca;
   ca.Bs = Bs;
   ca.ldb = 3 * cfg.tile;
@@ -338,11 +368,14 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   ca.err = err;
   ca.d = d;
   ca.e = e;
-  int grid = std::min<int>(ca.ngroups, chase_max_groups_resident(cfg.tile, cfg.sweep_width));
+  int grid = chase_grid(ca.ngroups, cfg.tile, cfg.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
   HIPCHK(launch_chase(ca, grid, st));
+  g_timing.mark(4, st);
   if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 16, st));
+  g_timing.mark(5, st);
+  g_timing.valid = g_timing.enabled;
   return SVDV_OK;
 }
 
@@ -446,7 +479,11 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   ca.err = (int*)(ws + L.err);
   ca.d = d;
   ca.e = e ? e : (double*)(ws + L.e);
-  int grid = std::min<int>(ca.ngroups, chase_max_groups_resident((int)b, c.sweep_width));
+  if (const char* env = getenv("SVDV_CHASE_GROUPS")) {  // debugging aid: run only the first groups
+    const int cap = atoi(env);
+    if (cap > 0 && cap < ca.ngroups) ca.ngroups = cap;
+  }
+  int grid = chase_grid(ca.ngroups, (int)b, c.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
   HIPCHK(launch_chase(ca, grid, st));
@@ -526,6 +563,30 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
   return SVDV_OK;
 }
 
+int svdv_timing(int enable) {
+  g_timing.enabled = enable != 0;
+  g_timing.valid = false;
+  return SVDV_OK;
+}
+
+int svdv_last_timing(double* ms, int n) {
+  if (!ms || n < 0) return fail(SVDV_ERR_INVALID_ARG, "bad output array");
+  if (!g_timing.valid) return fail(SVDV_ERR_INVALID_ARG, "no timed call recorded (enable svdv_timing first)");
+  HIPCHK(hipEventSynchronize(g_timing.ev[5]));
+  int k = 0;
+  for (int i = 0; i < 5 && k < n; ++i, ++k) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, g_timing.ev[i], g_timing.ev[i + 1]));
+    ms[k] = t;
+  }
+  if (k < n) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, g_timing.ev[0], g_timing.ev[5]));
+    ms[k++] = t;
+  }
+  return k;
+}
+
 int svdv_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : g_ws) {
@@ -540,3 +601,37 @@ int svdv_release(void) {
 }
 
 }  // extern "C"
+
+// Debugging aid (not part of the public header): run the bulge chase on a band
+// and copy the whole chase storage (n x 3b, row-major) to Bs_out (device).
+extern "C" int svdv_debug_chase(const double* band, int64_t n, int64_t b, int64_t ldband, double* Bs_out, int W,
+                                int ngroups_cap, int grid_cap) {
+  svdv_config c = default_config(n, n, SVDV_F64);
+  c.tile = (int32_t)b;
+  c.sweep_width = W;
+  hipStream_t st = nullptr;
+  Layout L = make_layout(n, n, 8, (int)b, 256, W, n);
+  char* ws = nullptr;
+  int rc = get_workspace(st, L.total, &ws);
+  if (rc) return rc;
+  double* Bs = (double*)(ws + L.Bs);
+  HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
+  ChaseArgs ca;
+  ca.Bs = Bs;
+  ca.ldb = 3 * b;
+  ca.n = n;
+  ca.b = (int32_t)b;
+  ca.W = W;
+  ca.ngroups = (int32_t)std::max<int64_t>(1, (n - 1 + W - 1) / W);
+  if (ngroups_cap > 0 && ngroups_cap < ca.ngroups) ca.ngroups = ngroups_cap;
+  ca.progress = (int*)(ws + L.progress);
+  ca.err = (int*)(ws + L.err);
+  ca.d = (double*)(ws + L.d);
+  ca.e = (double*)(ws + L.e);
+  int grid = chase_grid(ca.ngroups, (int)b, W);
+  if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
+  HIPCHK(launch_chase(ca, grid, st));
+  HIPCHK(hipMemcpyAsync(Bs_out, Bs, (size_t)n * 3 * b * 8, hipMemcpyDeviceToDevice, st));
+  return SVDV_OK;
+}

@@ -1,0 +1,244 @@
+// Stage-1 trailing update, the operation the paper's Algorithm 2 performs and
+// auto-tunes: apply the orthogonal factor of a panel to the trailing matrix.
+// Here it is done in compact-WY form, C <- (I - V T V^T)^T C = C - V (T^T (V^T C)),
+// one TSQR chunk (rows of V) and one 16*IB-column tile of C per workgroup:
+//
+//   pass 1  Z = V^T C        the NW waves split the chunk's 16-row slabs; every
+//                            wave accumulates a partial Z on the MFMA units,
+//                            prefetching the next slab while it multiplies;
+//   reduce  Z = sum of the NW partials in LDS (fixed order: deterministic);
+//   small   Z' = T^T Z       (vector FMAs, from LDS);
+//   pass 2  C -= V Z'        again slab-parallel over the waves, MFMA, with the
+//                            next slab prefetched.
+//
+// The paper's tunables map onto this kernel as: threads = NW * 64 (waves that
+// share a column tile and split its rows, like the split-K "K" of Algorithm 2),
+// inner_block = IB (16-column MFMA tiles per workgroup, like "CPB").
+#include <algorithm>
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace svdv {
+
+template <typename T, int KT, int IB>
+__device__ __forceinline__ void load_slab1(const LarfbArgs<T>& a, const T* V, int c, int Hc, int64_t colbase, int s,
+                                           int g, int nl, T (&cb)[IB][4], T (&av)[KT][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = s * 16 + acc_row<T>(g, i);
+    const bool rok = q < Hc;
+    const int64_t gr = rok ? a.rm.row(c, q) : 0;
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) {
+      const int64_t col = colbase + nt * 16 + nl;
+      cb[nt][i] = (rok && col < a.col1) ? a.M.at(gr, col) : T(0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < KT; ++mt) {
+      const int r = mt * 16 + nl;
+      av[mt][i] = (rok && r < a.k) ? V[q + (int64_t)r * a.ldv] : T(0);
+    }
+  }
+}
+
+template <typename T, int KT, int IB>
+__device__ __forceinline__ void load_slab2(const LarfbArgs<T>& a, const T* V, int c, int Hc, int64_t colbase, int s,
+                                           int g, int nl, T (&cd)[IB][4], T (&va)[KT][4], int64_t (&grow)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = s * 16 + acc_row<T>(g, i);
+    const bool rok = q < Hc;
+    grow[i] = rok ? a.rm.row(c, q) : -1;
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) {
+      const int64_t col = colbase + nt * 16 + nl;
+      cd[nt][i] = (rok && col < a.col1) ? a.M.at(grow[i], col) : T(0);
+    }
+  }
+  const int qa = s * 16 + nl;
+  const bool aok = qa < Hc;
+#pragma unroll
+  for (int ot = 0; ot < KT; ++ot)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ot * 16 + acc_row<T>(g, i);
+      va[ot][i] = (aok && r < a.k) ? -V[qa + (int64_t)r * a.ldv] : T(0);
+    }
+}
+
+template <typename T, int KT, int IB, int NW>
+__global__ void __launch_bounds__(NW * 64) k_larfb(LarfbArgs<T> a) {
+  typedef typename Acc<T>::type AccT;
+  constexpr int KR = KT * 16, CB = IB * 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Zs = reinterpret_cast<T*>(smem_raw);  // [NW][KR][CB] partial sums; slot 0 then holds Z
+  T* Zp = Zs + (size_t)NW * KR * CB;       // [KR][CB] Z' = T^T Z
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, nl = lane & 15;
+  const int c = blockIdx.y;
+  const int64_t row0 = (int64_t)c * a.chunk_rows;
+  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
+  const int k = a.k;
+  const int64_t colbase = a.col0 + (int64_t)blockIdx.x * CB;
+  const T* V = a.V + row0;
+  const T* Tm = a.Tm + (int64_t)c * a.ldt * a.ldt;
+  const int nslab = (Hc + 15) >> 4;
+
+  // ---------------- pass 1: partial Z = V^T C over this wave's slabs ----------------
+  AccT Z[KT][IB];
+#pragma unroll
+  for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+  {
+    T cbA[IB][4], avA[KT][4], cbB[IB][4], avB[KT][4];
+    auto mul = [&](T (&cb)[IB][4], T (&av)[KT][4]) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(av[mt][i], cb[nt][i], Z[mt][nt]);
+    };
+    int s = wv;
+    if (s < nslab) load_slab1<T, KT, IB>(a, V, c, Hc, colbase, s, g, nl, cbA, avA);
+    for (; s < nslab; s += 2 * NW) {
+      const int s1 = s + NW;
+      if (s1 < nslab) load_slab1<T, KT, IB>(a, V, c, Hc, colbase, s1, g, nl, cbB, avB);
+      mul(cbA, avA);
+      if (s1 >= nslab) break;
+      const int s2 = s1 + NW;
+      if (s2 < nslab) load_slab1<T, KT, IB>(a, V, c, Hc, colbase, s2, g, nl, cbA, avA);
+      mul(cbB, avB);
+    }
+  }
+  // ---------------- reduce the NW partials (fixed order) ----------------
+  {
+    T* mine = Zs + (size_t)wv * KR * CB;
+#pragma unroll
+    for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mine[(mt * 16 + acc_row<T>(g, r)) * CB + nt * 16 + nl] = Z[mt][nt][r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+    T acc = Zs[e];
+    for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
+    Zs[e] = acc;
+  }
+  __syncthreads();
+  // ---------------- Z' = T^T Z (T upper triangular, k x k) ----------------
+  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+    const int i = e / CB, col = e - i * CB;
+    T acc = T(0);
+    if (i < k)
+      for (int l = 0; l <= i; ++l) acc += Tm[l + (int64_t)i * a.ldt] * Zs[l * CB + col];
+    Zp[e] = acc;
+  }
+  __syncthreads();
+
+  // ---------------- pass 2: C -= V Z' ----------------
+  T zb[KT][4][IB];
+#pragma unroll
+  for (int ot = 0; ot < KT; ++ot)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) zb[ot][i][nt] = Zp[(ot * 16 + acc_row<T>(g, i)) * CB + nt * 16 + nl];
+
+  T cdA[IB][4], vaA[KT][4], cdB[IB][4], vaB[KT][4];
+  int64_t grA[4], grB[4];
+  auto upd = [&](T (&cd)[IB][4], T (&va)[KT][4], int64_t (&gr)[4]) {
+    AccT acc[IB];
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) acc[nt] = AccT{cd[nt][0], cd[nt][1], cd[nt][2], cd[nt][3]};
+#pragma unroll
+    for (int ot = 0; ot < KT; ++ot)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) acc[nt] = mfma16(va[ot][i], zb[ot][i][nt], acc[nt]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (gr[i] < 0) continue;
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) {
+        const int64_t col = colbase + nt * 16 + nl;
+        if (col < a.col1) a.M.at(gr[i], col) = acc[nt][i];
+      }
+    }
+  };
+  int s = wv;
+  if (s < nslab) load_slab2<T, KT, IB>(a, V, c, Hc, colbase, s, g, nl, cdA, vaA, grA);
+  for (; s < nslab; s += 2 * NW) {
+    const int s1 = s + NW;
+    if (s1 < nslab) load_slab2<T, KT, IB>(a, V, c, Hc, colbase, s1, g, nl, cdB, vaB, grB);
+    upd(cdA, vaA, grA);
+    if (s1 >= nslab) break;
+    const int s2 = s1 + NW;
+    if (s2 < nslab) load_slab2<T, KT, IB>(a, V, c, Hc, colbase, s2, g, nl, cdA, vaA, grA);
+    upd(cdB, vaB, grB);
+  }
+}
+
+template <typename T, int KT, int IB, int NW>
+static hipError_t launch_larfb_nw(const LarfbArgs<T>& a, hipStream_t st) {
+  if constexpr (larfb_valid<T>(KT, IB, NW)) {
+    constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+    static bool configured = false;
+    if (!configured) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_larfb<T, KT, IB, NW>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      configured = true;
+    }
+    const int64_t ncols = a.col1 - a.col0;
+    const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), (unsigned)a.P);
+    hipLaunchKernelGGL((k_larfb<T, KT, IB, NW>), grid, dim3(NW * 64), lds, st, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidConfiguration;
+  }
+}
+
+template <typename T, int KT, int IB>
+static hipError_t launch_larfb_ib(int nw, const LarfbArgs<T>& a, hipStream_t st) {
+  switch (nw) {
+    case 1: return launch_larfb_nw<T, KT, IB, 1>(a, st);
+    case 2: return launch_larfb_nw<T, KT, IB, 2>(a, st);
+    case 4: return launch_larfb_nw<T, KT, IB, 4>(a, st);
+    case 8: return launch_larfb_nw<T, KT, IB, 8>(a, st);
+    case 16: return launch_larfb_nw<T, KT, IB, 16>(a, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T, int KT>
+static hipError_t launch_larfb_kt(int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
+  switch (ib) {
+    case 1: return launch_larfb_ib<T, KT, 1>(nw, a, st);
+    case 2: return launch_larfb_ib<T, KT, 2>(nw, a, st);
+    case 4: return launch_larfb_ib<T, KT, 4>(nw, a, st);
+    case 8: return launch_larfb_ib<T, KT, 8>(nw, a, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T>
+hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
+  if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
+  switch (tile) {
+    case 16: return launch_larfb_kt<T, 1>(nw, ib, a, st);
+    case 32: return launch_larfb_kt<T, 2>(nw, ib, a, st);
+    case 64: return launch_larfb_kt<T, 4>(nw, ib, a, st);
+    case 128: return launch_larfb_kt<T, 8>(nw, ib, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_larfb<float>(int, int, int, const LarfbArgs<float>&, hipStream_t);
+template hipError_t launch_larfb<double>(int, int, int, const LarfbArgs<double>&, hipStream_t);
+
+}  // namespace svdv

@@ -21,6 +21,17 @@ def banner(msg: str):
     sys.stdout.flush()
 
 
+def valid_config(svdv, m, n, dtype, tile, sweep_width=1):
+    """A runnable configuration for this tile: the first (threads, inner_block) pair
+    in a fixed preference order that the library accepts."""
+    for threads, ib in [(256, 2), (256, 1), (128, 2), (128, 1), (64, 1), (512, 1)]:
+        for sw in (sweep_width, 2, 1):
+            cfg = svdv.Config(tile=tile, threads=threads, inner_block=ib, sweep_width=sw)
+            if svdv.check_config(m, n, dtype, cfg):
+                return cfg
+    return None
+
+
 def to_dev(a: np.ndarray, torch, fortran: bool = False):
     t = torch.from_numpy(np.ascontiguousarray(a))
     if fortran:

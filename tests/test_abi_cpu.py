@@ -58,7 +58,7 @@ def test_config_space_validity_rules():
     assert not svdv.check_config(256, 256, "float64", svdv.Config(tile=128))
     assert svdv.check_config(256, 256, "float32", svdv.Config(tile=128, threads=256, inner_block=1, sweep_width=2))
     assert not svdv.check_config(256, 256, "float32", svdv.Config(tile=128, threads=1024, inner_block=8))
-    assert svdv.check_config(256, 256, "float64", svdv.Config(tile=16, threads=64, inner_block=8, sweep_width=8))
+    assert svdv.check_config(256, 256, "float64", svdv.Config(tile=16, threads=64, inner_block=2, sweep_width=8))
     assert not svdv.check_config(256, 256, "float32", svdv.Config(tile=128, sweep_width=8))
     d = svdv.default_config(4096, 4096, "float32")
     assert svdv.check_config(4096, 4096, "float32", d)

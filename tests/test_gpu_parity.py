@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import banner, gate, sigma_errors, to_dev, torch_cuda
+from gpu_util import banner, gate, sigma_errors, to_dev, torch_cuda, valid_config
 
 pytestmark = pytest.mark.gpu
 
@@ -53,8 +53,8 @@ def test_stage_band_matches_oracle_up_to_signs(n, tile):
     svdv = _svdv()
     a = workloads.gaussian(n, n, cfg_id=70, dtype="float64")
     banner(f"stage_band float64 n={n} tile={tile}")
-    band = svdv.stage_band(to_dev(a, torch, fortran=True), config=svdv.Config(tile=tile, threads=256,
-                                                                               inner_block=2, sweep_width=1))
+    cfg = valid_config(svdv, n, n, "float64", tile)
+    band = svdv.stage_band(to_dev(a, torch, fortran=True), config=cfg)
     torch.cuda.synchronize()
     band = band.cpu().numpy()
     ref = oracle.band_reduce(a, tile)
@@ -75,7 +75,8 @@ def test_stage_band_rectangular_and_float32():
     for (m, n, dt) in [(150, 90, "float64"), (90, 150, "float64"), (300, 300, "float32")]:
         a = workloads.as_dtype(workloads.gaussian(m, n, cfg_id=71, dtype=dt), dt)
         banner(f"stage_band {dt} m={m} n={n}")
-        band = svdv.stage_band(to_dev(a, torch, fortran=True), config=svdv.Config(tile=32)).cpu().numpy()
+        band = svdv.stage_band(to_dev(a, torch, fortran=True),
+                               config=valid_config(svdv, m, n, dt, 32)).cpu().numpy()
         k = min(m, n)
         full = np.zeros((k, k))
         for d in range(33):
@@ -148,7 +149,7 @@ def test_cfg0_known_spectrum_float64():
     a = workloads.cfg0_matrix()
     banner("end-to-end cfg0 256x256 float64 tile 32")
     s = svdv.svd_values(to_dev(a, torch, fortran=True), config=svdv.Config(tile=32, threads=256, inner_block=1,
-                                                                            sweep_width=1)).cpu().numpy()
+                                                                            sweep_width=1)).cpu().numpy()  # plain
     ref = oracle.svd_values(a)
     gate("float64", s, ref)
     assert np.max(np.abs(s - workloads.cfg0_spectrum())) <= 1e-12
@@ -161,9 +162,9 @@ def test_cfg0_known_spectrum_float64():
 def test_end_to_end_matches_oracle(dtype, m, n, tile):
     torch = torch_cuda()
     svdv = _svdv()
-    cfg = svdv.Config(tile=tile, threads=256, inner_block=2, sweep_width=4 if tile < 128 else 2)
-    if not svdv.check_config(m, n, dtype, cfg):
-        pytest.skip("configuration not built for this dtype")
+    cfg = valid_config(svdv, m, n, dtype, tile, sweep_width=4)
+    if cfg is None:
+        pytest.skip("no configuration built for this tile and dtype")
     a = workloads.as_dtype(workloads.gaussian(m, n, cfg_id=73, dtype=dtype), dtype)
     banner(f"end-to-end {dtype} m={m} n={n} tile={tile}")
     s = svdv.svd_values(to_dev(a, torch, fortran=True), config=cfg).cpu().numpy()
