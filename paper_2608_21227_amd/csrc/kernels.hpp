@@ -87,11 +87,14 @@ struct ChaseArgs {
   int32_t b;
   int32_t W;           // sweeps per workgroup (sweep width)
   int32_t ngroups;     // ceil((n-1) / W)
-  int32_t* progress;   // per group: tasks completed by its last sweep (n entries, zeroed before launch)
+  int32_t* progress;   // per group: tasks completed by its last sweep; entry ngroups is the
+                       // group ticket (ngroups + 1 entries, zeroed before launch)
   int32_t* err;        // set when a bounded wait gives up
   double* d;
   double* e;
+  double* dummy;       // per-thread dummy store targets of the pipelined kernel (kChaseDummy doubles)
 };
+constexpr int64_t kChaseDummy = 2048 * 384;
 size_t chase_lds_bytes(int b, int W);
 int chase_max_groups_resident(int b, int W);
 hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st);

@@ -16,8 +16,11 @@
 // Schedule: sweeps are cut into groups of W consecutive sweeps; one workgroup
 // (W waves) owns a group and advances its sweeps in lockstep -- at step t the
 // wave of sweep s0+i runs task t-3i -- with a workgroup barrier between steps.
-// Groups are handed out round-robin to a persistent grid; group g waits for
-// group g-1's last sweep through a progress counter.  Band data crosses
+// A persistent grid takes groups in increasing order from a ticket counter, so
+// the predecessor of every group being worked on is held by a workgroup that is
+// already running: no schedule can wait on a workgroup that was never made
+// resident, whatever the occupancy.  Group g waits for group g-1's last sweep
+// through a progress counter.  Band data crosses
 // workgroups (and XCDs, whose L2 caches are not coherent with each other), so
 // every band access is a relaxed device-scope atomic (coherent at device
 // level), and progress is published only after the step's stores completed.
@@ -25,6 +28,21 @@
 #include "kernels.hpp"
 
 namespace svdv {
+
+// Optional step trace of group 0 (diagnostic builds only, -DSVDV_CHASE_TRACE):
+// eight timestamps per step of the 100 MHz real-time counter.
+#ifdef SVDV_CHASE_TRACE
+__device__ uint64_t g_chase_trace[8 * 1024];
+#define CHASE_MARK(gi, t, k)                                                   \
+  do {                                                                         \
+    if ((gi) == 0 && threadIdx.x == 0 && (t) < 1024)                           \
+      g_chase_trace[(t) * 8 + (k)] = __builtin_amdgcn_s_memrealtime();         \
+  } while (0)
+#else
+#define CHASE_MARK(gi, t, k) \
+  do {                       \
+  } while (0)
+#endif
 
 __device__ __forceinline__ double bld(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -166,9 +184,26 @@ __device__ void chase_task(const ChaseCtx& X, int64_t p, int64_t c, double* tile
   }
 }
 
+// Next group for this workgroup (ticket in progress[ngroups], zeroed with the
+// progress counters).  Every thread returns the same value.
+__device__ __forceinline__ int next_group(const ChaseArgs& a) {
+  __shared__ int s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(a.progress + a.ngroups, 1);
+  __syncthreads();
+  const int gi = s_ticket;
+  __syncthreads();
+  return gi;
+}
+
 __device__ __forceinline__ int ntasks_of(int64_t s, int64_t n, int b) {
   if (s >= n - 1) return 0;
   return (int)((n - 1 - s + b - 1) / b);
+}
+
+template <int B>
+__device__ __forceinline__ int ntasks_b(int64_t s, int64_t n) {
+  const int r = (int)(n - 1 - s);
+  return r > 0 ? (r + B - 1) / B : 0;
 }
 
 size_t chase_lds_bytes(int b, int W) {
@@ -189,7 +224,9 @@ __global__ void k_chase(ChaseArgs a) {
   const int64_t n = a.n;
   __shared__ int s_giveup;
 
-  for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+  for (;;) {
+    const int gi = next_group(a);
+    if (gi >= a.ngroups) break;
     const int64_t s0 = (int64_t)gi * W;
     const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
     int tend = 0;
@@ -262,7 +299,7 @@ template <int B>
 struct WinGeom {
   static constexpr int LO = B - 1;
   static constexpr int RW = 3 * B;      // entries of a band row (global and LDS)
-  static constexpr int RS = 3 * B + 1;  // LDS slot stride (odd: fewer bank conflicts)
+  static constexpr int RS = 3 * B + 2;  // LDS slot stride (see win_task)
   // the windowed kernel always runs at least 4 waves (the extra ones only move rows)
   static constexpr int MIN_WAVES = 4;
   static constexpr int PF = (B * RW + 64 * MIN_WAVES - 1) / (64 * MIN_WAVES);  // prefetch registers per thread
@@ -272,87 +309,114 @@ __host__ __device__ inline int win_rows(int b, int W) { return (3 * W + 2) * b +
 
 size_t chase_win_lds_bytes(int b, int W) {
   if (b != 16 && b != 32) return (size_t)1 << 40;
-  return ((size_t)win_rows(b, W) * (3 * b + 1) + (size_t)(W > 4 ? W : 4) * 64) * sizeof(double);
+  return (size_t)(win_rows(b, W) + 1) * (3 * b + 2) * sizeof(double);  // ring + zero slot
 }
 
-template <int B>
-__device__ __forceinline__ double& welem(double* win, int R, int64_t i, int64_t j) {
-  return win[(int)((uint64_t)i % (uint64_t)R) * WinGeom<B>::RS + (int)(j - i + WinGeom<B>::LO)];
+// Ring slot of row r: (r - base) mod R (base <= every row the window holds;
+// the difference is below 2^31).  Column j of row r sits at offset j - r + (B-1)
+// of the slot.
+__device__ __forceinline__ int ring_slot(int64_t r, int64_t base, int R) {
+  return (int)((uint32_t)(r - base) % (uint32_t)R);
 }
 
-template <int B>
-__device__ void win_task(double* win, int R, int64_t n, int64_t p, int64_t c, double* vb) {
-  constexpr int RS = WinGeom<B>::RS, LO = WinGeom<B>::LO;
-  const int lane = threadIdx.x & 63;
-  const int L = (int)((n - c) < B ? (n - c) : B);
-  const int64_t rend = c + L < n ? c + L : n;
-  const int64_t cend = c + L + B < n ? c + L + B : n;
+// Value of lane l of v (a wave-uniform result).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 
-  // right reflector on row p, columns c..c+L-1
-  double x = lane < L ? welem<B>(win, R, p, c + lane) : 0.0;
-  double ss = wave_sum((lane >= 1 && lane < L) ? x * x : 0.0);
-  double alpha = __shfl(x, 0, kWave);
-  double beta = alpha, tau = 0.0, scal = 0.0;
+// Householder reflector H = I - tau v v^T with H x = beta e_1, for the vector x
+// held one entry per lane (lanes >= L hold 0).  v is returned per lane (v_0 = 1,
+// zero beyond L); x = 0 below its first entry gives tau = 0 (H = I).
+__device__ __forceinline__ void wave_reflector(double x, int lane, int L, double& beta, double& tau, double& v) {
+  const double ss = wave_sum((lane >= 1 && lane < L) ? x * x : 0.0);
+  const double alpha = lane_value(x, 0);
+  double scal = 0.0;
+  beta = alpha;
+  tau = 0.0;
   if (ss > 0.0) {
     const double nrm = sqrt(alpha * alpha + ss);
     beta = alpha >= 0.0 ? -nrm : nrm;
     scal = 1.0 / (alpha - beta);
     tau = (beta - alpha) / beta;
   }
-  if (lane < L) {
-    vb[lane] = lane == 0 ? 1.0 : x * scal;
-    welem<B>(win, R, p, c + lane) = lane == 0 ? beta : 0.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  v = lane < L ? (lane == 0 ? 1.0 : x * scal) : 0.0;
+}
+
+// One task (p, c) on the window, executed by one wave.  The reflector entries are
+// broadcast into scalar registers and every lane loads its whole row (right
+// update) or column (left update) into registers before using it, so each
+// update costs one round of LDS latency rather than one per entry.  The loops
+// run over all B entries whatever L is: the reflector is zero beyond L, the
+// right update then reads and rewrites band positions past column n (zeros),
+// and the left update reads rows past n from the zero slot `zs` (a slot kept at
+// zero), so no entry changes and no loop needs a branch.  The slot stride is
+// 3B+2: a column of the band walks the slots with stride 3B+1 (odd), which
+// spreads the lanes of the right update over distinct banks.
+template <int B>
+__device__ void win_task(double* win, int R, int zs, int64_t base, int64_t n, int64_t p, int64_t c) {
+  constexpr int RS = WinGeom<B>::RS, LO = WinGeom<B>::LO;
+  const int lane = threadIdx.x & 63;
+  const int L = (int)((n - c) < B ? (n - c) : B);
+  const int nr = (int)(c + L - p - 1);                              // rows p+1 .. c+L-1
+  const int nq = (int)((c + L + B < n ? c + L + B : n) - c - 1);   // columns c+1 .. min(c+L+B, n)-1
+  const int sp = ring_slot(p, base, R), sc = ring_slot(c, base, R);
+  const int dc = (int)(c - p);
+
+  // right reflector on row p, columns c..c+L-1 (element (p, c+l) at rowp[l])
+  double* rowp = win + sp * RS + (dc + LO);
+  double x = lane < L ? rowp[lane] : 0.0;
+  double beta, tau, v;
+  wave_reflector(x, lane, L, beta, tau, v);
+  if (lane < L) rowp[lane] = lane == 0 ? beta : 0.0;
   if (tau != 0.0) {
-    const int64_t r = p + 1 + lane;
-    if (r < rend) {
-      double* row = win + (int)((uint64_t)r % (uint64_t)R) * RS + (int)(c - r + LO);
+    double vr[B];
+#pragma unroll
+    for (int l = 0; l < B; ++l) vr[l] = lane_value(v, l);
+    if (lane < nr) {
+      int sr = sp + 1 + lane;
+      sr = sr >= R ? sr - R : sr;
+      double* row = win + sr * RS + (dc - 1 - lane + LO);  // element (p+1+lane, c+l) at row[l]
+      double xr[B];
+#pragma unroll
+      for (int l = 0; l < B; ++l) xr[l] = row[l];
       double dot = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < L; ++l) dot += row[l] * vb[l];
+#pragma unroll
+      for (int l = 0; l < B; ++l) dot += xr[l] * vr[l];
       const double td = tau * dot;
-#pragma unroll 8
-      for (int l = 0; l < L; ++l) row[l] -= td * vb[l];
+#pragma unroll
+      for (int l = 0; l < B; ++l) row[l] = xr[l] - td * vr[l];
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
-  // left reflector on column c, rows c..c+L-1
-  x = lane < L ? welem<B>(win, R, c + lane, c) : 0.0;
-  ss = wave_sum((lane >= 1 && lane < L) ? x * x : 0.0);
-  alpha = __shfl(x, 0, kWave);
-  beta = alpha;
-  tau = 0.0;
-  scal = 0.0;
-  if (ss > 0.0) {
-    const double nrm = sqrt(alpha * alpha + ss);
-    beta = alpha >= 0.0 ? -nrm : nrm;
-    scal = 1.0 / (alpha - beta);
-    tau = (beta - alpha) / beta;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  if (lane < L) {
-    vb[lane] = lane == 0 ? 1.0 : x * scal;
-    welem<B>(win, R, c + lane, c) = lane == 0 ? beta : 0.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // left reflector on column c, rows c..c+L-1 (element (c+l, c) at slot(c+l), offset LO-l)
+  int sx = sc + lane;
+  sx = sx >= R ? sx - R : sx;
+  x = lane < L ? win[sx * RS + LO - lane] : 0.0;
+  wave_reflector(x, lane, L, beta, tau, v);
+  if (lane < L) win[sx * RS + LO - lane] = lane == 0 ? beta : 0.0;
   if (tau != 0.0) {
-    const int64_t q = c + 1 + lane;
-    if (q < cend) {
-      const int sc = (int)((uint64_t)c % (uint64_t)R);
+    double vr[B];
+#pragma unroll
+    for (int l = 0; l < B; ++l) vr[l] = lane_value(v, l);
+    if (lane < nq) {
+      int so[B];     // slot of row c+l (the zero slot past row n-1)
+      double xc[B];  // element (c+l, c+1+lane) at offset 1+lane-l+LO of that slot
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        int sl = sc + l;
+        sl = sl >= R ? sl - R : sl;
+        so[l] = l < L ? sl : zs;
+        xc[l] = win[so[l] * RS + 1 + lane - l + LO];
+      }
       double dot = 0.0;
-      for (int l = 0; l < L; ++l) {
-        int sl = sc + l;
-        sl = sl >= R ? sl - R : sl;
-        dot += vb[l] * win[sl * RS + (int)(q - c - l + LO)];
-      }
+#pragma unroll
+      for (int l = 0; l < B; ++l) dot += vr[l] * xc[l];
       const double td = tau * dot;
-      for (int l = 0; l < L; ++l) {
-        int sl = sc + l;
-        sl = sl >= R ? sl - R : sl;
-        win[sl * RS + (int)(q - c - l + LO)] -= td * vb[l];
-      }
+#pragma unroll
+      for (int l = 0; l < B; ++l) win[so[l] * RS + 1 + lane - l + LO] = xc[l] - td * vr[l];
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -370,24 +434,26 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
   const int W = a.W;
   const int R = win_rows(B, W);
   double* win = lds;
+  for (int e = threadIdx.x; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
   const int wv = threadIdx.x >> 6;
-  double* vb = lds + (size_t)R * RS + wv * 64;
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   __shared__ int s_giveup;
 
-  for (int gi = blockIdx.x; gi < a.ngroups; gi += gridDim.x) {
+  for (;;) {
+    const int gi = next_group(a);
+    if (gi >= a.ngroups) break;
     const int64_t s0 = (int64_t)gi * W;
     const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
     int tend = 0;
     for (int i = 0; i < nsw; ++i) {
-      const int te = 3 * i + ntasks_of(s0 + i, n, B);
+      const int te = 3 * i + ntasks_b<B>(s0 + i, n);
       tend = te > tend ? te : tend;
     }
-    const int prev_total = gi > 0 ? ntasks_of(s0 - 1, n, B) : 0;
-    const int last_total = ntasks_of(s0 + nsw - 1, n, B);
-    const int first_total = ntasks_of(s0, n, B);
+    const int prev_total = gi > 0 ? ntasks_b<B>(s0 - 1, n) : 0;
+    const int last_total = ntasks_b<B>(s0 + nsw - 1, n);
+    const int first_total = ntasks_b<B>(s0, n);
     // rows the group's first sweep needs up to (and including) step t: [s0, front_end(t))
     auto front_end = [&](int t) -> int64_t {
       const int tt = t < first_total - 1 ? t : first_total - 1;
@@ -418,7 +484,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
     for (int64_t e = tid; e < (hi - lo) * RW; e += nthr) {
       const int64_t r = lo + e / RW;
       const int col = (int)(e % RW);
-      win[(int)((uint64_t)r % (uint64_t)R) * RS + col] = bld(a.Bs + r * a.ldb + col);
+      win[ring_slot(r, 0, R) * RS + col] = bld(a.Bs + r * a.ldb + col);
     }
     __syncthreads();
 
@@ -439,10 +505,10 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
       if (wv < nsw) {
         const int64_t s = s0 + wv;
         const int jt = t - 3 * wv;
-        if (jt >= 0 && jt < ntasks_of(s, n, B)) {
+        if (jt >= 0 && jt < ntasks_b<B>(s, n)) {
           const int64_t c = s + 1 + (int64_t)jt * B;
           const int64_t p = jt == 0 ? s : c - B;
-          win_task<B>(win, R, n, p, c, vb);
+          win_task<B>(win, R, R, 0, n, p, c);
         }
       }
       __syncthreads();
@@ -452,7 +518,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
       int64_t nlo = n;
       for (int i = 0; i < nsw; ++i) {
         const int jn = t + 1 - 3 * i;
-        if (jn < ntasks_of(s0 + i, n, B)) {
+        if (jn < ntasks_b<B>(s0 + i, n)) {
           const int64_t f = sweep_front(s0 + i, jn, B);
           nlo = f < nlo ? f : nlo;
         }
@@ -461,7 +527,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
       for (int64_t e = tid; e < (nlo - lo) * RW; e += nthr) {
         const int64_t r = lo + e / RW;
         const int col = (int)(e % RW);
-        bst(a.Bs + r * a.ldb + col, win[(int)((uint64_t)r % (uint64_t)R) * RS + col]);
+        bst(a.Bs + r * a.ldb + col, win[ring_slot(r, 0, R) * RS + col]);
       }
       lo = nlo;
 #pragma unroll
@@ -469,7 +535,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
         const int64_t e = tid + (int64_t)k * nthr;
         if (e < npf) {
           const int64_t r = hi + e / RW;
-          win[(int)((uint64_t)r % (uint64_t)R) * RS + (int)(e % RW)] = pf[k];
+          win[ring_slot(r, 0, R) * RS + (int)(e % RW)] = pf[k];
         }
       }
       hi = nhi;
@@ -485,12 +551,210 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
     for (int64_t e = tid; e < (hi - lo) * RW; e += nthr) {
       const int64_t r = lo + e / RW;
       const int col = (int)(e % RW);
-      bst(a.Bs + r * a.ldb + col, win[(int)((uint64_t)r % (uint64_t)R) * RS + col]);
+      bst(a.Bs + r * a.ldb + col, win[ring_slot(r, 0, R) * RS + col]);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0)
       __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined windowed chase (b = 16): the same window, with the global-memory
+// traffic taken off the step's critical path.
+// ---------------------------------------------------------------------------
+//
+// Rows for step t+D are requested at step t into a ring of D register sets and
+// written into the window at the end of step t+D-1, so a load has D-1 compute
+// steps to arrive.  Rows leave the window at most b per step, with one store
+// instruction per thread per step (threads with nothing to write store to a
+// private dummy word), so every step issues the same number of loads and stores
+// and the waits the compiler places for the ring stay exact.  The progress of
+// step t-D is published at the end of step t: by then the loads of step t-D+1
+// have completed, and the write-back stores of step t-D were issued before them.
+// A group polls its predecessor once per D steps, for the progress the next D
+// steps of loads need.
+
+constexpr int kPipeThreads = 384;  // 6 waves: up to 6 sweeps, the rest move rows
+
+__host__ __device__ inline int pipe_rows(int b, int W, int D) { return (3 * W + D + 4) * b; }
+
+size_t chase_pipe_lds_bytes(int b, int W, int D) {
+  return (size_t)(pipe_rows(b, W, D) + 1) * (3 * b + 2) * sizeof(double);  // ring + zero slot
+}
+
+template <int B, int D>
+__global__ void __launch_bounds__(kPipeThreads) k_chase_pipe(ChaseArgs a) {
+  constexpr int LO = B - 1, RW = 3 * B, RS = RW + 2, NT = kPipeThreads;
+  constexpr int PF = (B * RW + NT - 1) / NT;  // loads (and stores) per thread per step
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int s_flag;
+  __shared__ int64_t s_lo[D + 1];
+  __shared__ int s_done[D + 1];
+  const int W = a.W;
+  const int R = pipe_rows(B, W, D);
+  double* win = lds;
+  for (int e = threadIdx.x; e < RS; e += NT) win[R * RS + e] = 0.0;  // zero slot
+  const int wv = threadIdx.x >> 6, tid = threadIdx.x;
+  double* dummy = a.dummy + (size_t)blockIdx.x * NT + tid;
+  const int64_t n = a.n;
+
+  for (;;) {
+    const int gi = next_group(a);
+    if (gi >= a.ngroups) break;
+    const int64_t s0 = (int64_t)gi * W;
+    const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
+    const int64_t sl = s0 + nsw - 1;
+    int tend = 0;
+    for (int i = 0; i < nsw; ++i) {
+      const int te = 3 * i + ntasks_b<B>(s0 + i, n);
+      tend = te > tend ? te : tend;
+    }
+    const int prev_total = gi > 0 ? ntasks_b<B>(s0 - 1, n) : 0;
+    const int last_total = ntasks_b<B>(sl, n);
+    const int first_total = ntasks_b<B>(s0, n);
+    const int64_t base = s0 + 1 - R;  // slot(r) = (r - base) mod R; prefetch blocks never wrap
+    auto slot = [&](int64_t r) -> int { return ring_slot(r, base, R); };
+    auto front_end = [&](int t) -> int64_t {
+      const int tt = t < first_total - 1 ? t : first_total - 1;
+      const int64_t e = s0 + 1 + (int64_t)(tt + 1) * B;
+      return e < n ? e : n;
+    };
+    auto wait_prev = [&](int need) {
+      if (gi == 0 || threadIdx.x != 0) return;
+      need = need < prev_total ? need : prev_total;
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      while (__hip_atomic_load(&a.progress[gi - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull ||  // 10 s at 100 MHz
+            __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          atomicAdd(a.err, 1);
+          s_flag = 1;
+          return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    };
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    // rows the first D steps need, loaded directly
+    wait_prev(D + 3);
+    __syncthreads();
+    int64_t lo = s0;
+    const int64_t hi0 = s_flag ? s0 : front_end(D - 1);
+    for (int64_t e = tid; e < (hi0 - lo) * RW; e += NT) {
+      const int64_t r = lo + e / RW;
+      const int col = (int)(e % RW);
+      win[slot(r) * RS + col] = bld(a.Bs + r * a.ldb + col);
+    }
+    __syncthreads();
+    int published = 0;
+    double regs[D][PF];
+    for (int t0 = 0; t0 < tend && !s_flag; t0 += D) {
+      wait_prev(t0 + 2 * D + 3);
+      __syncthreads();
+      if (s_flag) break;
+#pragma unroll
+      for (int S = 0; S < D; ++S) {
+        const int t = t0 + S;
+        if (t >= tend) break;
+        CHASE_MARK(gi, t, 0);
+        // (1) request the rows of step t+D
+        {
+          const int64_t r0 = front_end(t + D - 1);
+          const int npf = (int)((front_end(t + D) - r0) * RW);
+#pragma unroll
+          for (int k = 0; k < PF; ++k) {
+            const int e = tid + k * NT;
+            const int64_t idx = e < npf ? r0 * a.ldb + e : 0;
+            regs[S][k] = bld(a.Bs + idx);
+          }
+        }
+        CHASE_MARK(gi, t, 1);
+        // (2) compute: wave i runs task t-3i of sweep s0+i
+        if (wv < nsw) {
+          const int64_t s = s0 + wv;
+          const int jt = t - 3 * wv;
+          if (jt >= 0 && jt < ntasks_b<B>(s, n)) {
+            const int64_t c = s + 1 + (int64_t)jt * B;
+            const int64_t p = jt == 0 ? s : c - B;
+            win_task<B>(win, R, R, base, n, p, c);
+          }
+        }
+        CHASE_MARK(gi, t, 2);
+        __syncthreads();
+        CHASE_MARK(gi, t, 3);
+        // (3) write back at most B rows no unfinished sweep touches again
+        {
+          int64_t nlo = n;
+          for (int i = 0; i < nsw; ++i) {
+            const int jn = t + 1 - 3 * i;
+            if (jn < ntasks_b<B>(s0 + i, n)) {
+              const int64_t f = sweep_front(s0 + i, jn, B);
+              nlo = f < nlo ? f : nlo;
+            }
+          }
+          const int64_t cap = front_end(t);
+          nlo = nlo < cap ? nlo : cap;
+          nlo = nlo < lo + B ? nlo : lo + B;
+          const int nwb = (int)((nlo - lo) * RW);
+#pragma unroll
+          for (int k = 0; k < PF; ++k) {
+            const int e = tid + k * NT;
+            const bool ok = e < nwb;
+            const int64_t r = lo + (ok ? e / RW : 0);
+            const int col = ok ? e % RW : 0;
+            const double v = win[(ok ? slot(r) : 0) * RS + col];
+            bst(ok ? a.Bs + r * a.ldb + col : dummy, v);
+          }
+          lo = nlo;
+        }
+        CHASE_MARK(gi, t, 4);
+        // (4) rows of step t+1 (requested at step t-D+1) into the window
+        if (t - D + 1 >= 0) {
+          const int64_t r0 = front_end(t);
+          const int nst = (int)((front_end(t + 1) - r0) * RW);
+#pragma unroll
+          for (int k = 0; k < PF; ++k) {
+            const int e = tid + k * NT;
+            if (e < nst) win[slot(r0 + e / RW) * RS + e % RW] = regs[(S + 1) % D][k];
+          }
+        }
+        if (tid == 0) {
+          int dl = t - 3 * (nsw - 1) + 1;
+          dl = dl < 0 ? 0 : (dl > last_total ? last_total : dl);
+          s_lo[t % (D + 1)] = lo;
+          s_done[t % (D + 1)] = dl;
+        }
+        CHASE_MARK(gi, t, 5);
+        __syncthreads();
+        CHASE_MARK(gi, t, 6);
+        // (5) publish the progress of step t-D
+        if (tid == 0 && t - D >= 0) {
+          const int64_t L = s_lo[(t - D) % (D + 1)];
+          int P = s_done[(t - D) % (D + 1)];
+          const int64_t byrows = L - sl - 1 >= 0 ? (L - sl - 1) / B + 1 : 0;
+          P = byrows < P ? (int)byrows : P;
+          P = P < last_total - 1 ? P : last_total - 1;
+          if (P > published) {
+            published = P;
+            __hip_atomic_store(&a.progress[gi], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        CHASE_MARK(gi, t, 7);
+      }
+    }
+    // flush the window and mark the group complete
+    const int64_t hi_end = front_end(tend);
+    for (int64_t e = tid; e < (hi_end - lo) * RW; e += NT) {
+      const int64_t r = lo + e / RW;
+      const int col = (int)(e % RW);
+      bst(a.Bs + r * a.ldb + col, win[slot(r) * RS + col]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
 }
@@ -503,18 +767,26 @@ __global__ void k_chase_extract(const double* __restrict__ Bs, int64_t ldb, int6
   }
 }
 
-static bool use_window(int b, int W) { return (b == 16 || b == 32) && chase_win_lds_bytes(b, W) <= 159 * 1024; }
+static bool use_pipe(int b, int W) { return b == 16 && W <= kPipeThreads / 64 && chase_pipe_lds_bytes(b, W, 3) <= 159 * 1024; }
+static bool use_window(int b, int W) {
+  return !use_pipe(b, W) && (b == 16 || b == 32) && chase_win_lds_bytes(b, W) <= 159 * 1024;
+}
 
 static const void* chase_fn(int b, int W) {
+  if (use_pipe(b, W)) return (const void*)k_chase_pipe<16, 3>;
   if (use_window(b, W)) return b == 16 ? (const void*)k_chase_win<16> : (const void*)k_chase_win<32>;
   return (const void*)k_chase;
 }
 
 static int chase_threads(int b, int W) {
+  if (use_pipe(b, W)) return kPipeThreads;
   return use_window(b, W) ? 64 * (W > WinGeom<16>::MIN_WAVES ? W : WinGeom<16>::MIN_WAVES) : 64 * W;
 }
 
-static size_t chase_launch_lds(int b, int W) { return use_window(b, W) ? chase_win_lds_bytes(b, W) : chase_lds_bytes(b, W); }
+static size_t chase_launch_lds(int b, int W) {
+  if (use_pipe(b, W)) return chase_pipe_lds_bytes(b, W, 3);
+  return use_window(b, W) ? chase_win_lds_bytes(b, W) : chase_lds_bytes(b, W);
+}
 
 static hipError_t chase_set_lds(const void* fn, size_t lds) {
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -540,7 +812,8 @@ hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st) {
   if (a.n > 1) {
     hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, st, a.progress, 0, (int64_t)a.ngroups + 1);
     const dim3 block(chase_threads(a.b, a.W));
-    if (fn == (const void*)k_chase_win<16>) hipLaunchKernelGGL(k_chase_win<16>, dim3(grid), block, lds, st, a);
+    if (fn == (const void*)k_chase_pipe<16, 3>) hipLaunchKernelGGL((k_chase_pipe<16, 3>), dim3(grid), block, lds, st, a);
+    else if (fn == (const void*)k_chase_win<16>) hipLaunchKernelGGL(k_chase_win<16>, dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_win<32>) hipLaunchKernelGGL(k_chase_win<32>, dim3(grid), block, lds, st, a);
     else hipLaunchKernelGGL(k_chase, dim3(grid), block, lds, st, a);
   }
@@ -551,3 +824,9 @@ hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st) {
 }
 
 }  // namespace svdv
+
+#ifdef SVDV_CHASE_TRACE
+extern "C" int svdv_chase_trace(uint64_t* out, int count) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(svdv::g_chase_trace), (size_t)count * 8);
+}
+#endif

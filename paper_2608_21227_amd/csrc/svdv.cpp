@@ -205,7 +205,7 @@ size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 // Persistent grid of the bulge chase: every workgroup must be resident at once.
 // SVDV_CHASE_GRID (debugging aid) caps it further, e.g. 1 = all groups in one workgroup.
 int chase_grid(int ngroups, int b, int W) {
-  int g = std::min<int>(ngroups, chase_max_groups_resident(b, W));
+  int g = std::min<int>({ngroups, chase_max_groups_resident(b, W), (int)(kChaseDummy / 384)});
   if (const char* env = getenv("SVDV_CHASE_GRID")) {
     const int cap = atoi(env);
     if (cap > 0) g = std::min(g, cap);
@@ -214,7 +214,7 @@ int chase_grid(int ngroups, int b, int W) {
 }
 
 struct Layout {
-  size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, total;
+  size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, dummy, total;
 };
 
 Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_width, int64_t ldw) {
@@ -239,6 +239,7 @@ Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_w
   L.d = take((size_t)N * 8);
   L.e = take((size_t)N * 8);
   L.work = take((size_t)(2 * N + 2) * 8);
+  L.dummy = take((size_t)kChaseDummy * 8);
   L.total = off;
   return L;
 }
@@ -368,6 +369,7 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   ca.err = err;
   ca.d = d;
   ca.e = e;
+  ca.dummy = (double*)(ws + L.dummy);
   int grid = chase_grid(ca.ngroups, cfg.tile, cfg.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
@@ -479,6 +481,7 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   ca.err = (int*)(ws + L.err);
   ca.d = d;
   ca.e = e ? e : (double*)(ws + L.e);
+  ca.dummy = (double*)(ws + L.dummy);
   if (const char* env = getenv("SVDV_CHASE_GROUPS")) {  // debugging aid: run only the first groups
     const int cap = atoi(env);
     if (cap > 0 && cap < ca.ngroups) ca.ngroups = cap;
@@ -628,6 +631,7 @@ extern "C" int svdv_debug_chase(const double* band, int64_t n, int64_t b, int64_
   ca.err = (int*)(ws + L.err);
   ca.d = (double*)(ws + L.d);
   ca.e = (double*)(ws + L.e);
+  ca.dummy = (double*)(ws + L.dummy);
   int grid = chase_grid(ca.ngroups, (int)b, W);
   if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
