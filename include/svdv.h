@@ -149,6 +149,9 @@ int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_d
  *   T  k x k upper triangular, column-major, leading dimension ldt.
  *   C  h x w, column-major, leading dimension ldc, updated in place.
  *   k  <= cfg->tile.  All three in `dtype`.
+ *   A reflector length (h for side 0, w for side 1) above 32768 / cfg->tile (the
+ *   rows one workgroup can hold in registers) runs the streaming form of the
+ *   kernel; a configuration without one returns SVDV_ERR_UNSUPPORTED.
  */
 int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* C, int64_t ldc, int64_t h, int64_t w,
                   int64_t k, int32_t dtype, int32_t side, void* stream, const svdv_config* cfg);

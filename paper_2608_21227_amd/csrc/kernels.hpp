@@ -37,27 +37,45 @@ struct LarfbArgs {
   const T* Tm;
   int64_t ldt;        // = TILE (per-chunk T is ldt x ldt)
   int32_t k;          // reflectors per chunk
+  int32_t vec;        // 1: view rows contiguous in memory and every 4-row group of C and V
+                      // 16-byte aligned (float only), so 4 rows load as one access
 };
 
-// Register estimate (32-bit registers per lane) of the trailing-update kernel:
-// the Z accumulators / Z' operands (KT x IB tiles), two slabs of C (IB) and V
-// (KT) in flight, the C accumulator of pass 2.
-// (calibrated against the compiler's resource report so that no valid
-// configuration spills registers to scratch)
+// Slabs (16 rows) per wave of the trailing update: enough for the largest chunk a
+// panel level can have (the chunk-QR capacity, 32768 / tile rows).
+constexpr int larfb_spw(int tile, int NW) { return ((32768 / tile + 15) / 16 + NW - 1) / NW; }
+// Register estimates (32-bit registers per lane), calibrated against the
+// compiler's resource report so that no configuration taken spills to scratch.
+//  register-strip kernel: the strip (SPW x IB tiles), V operands (SPW x KT tiles),
+//  Z and Z' (KT x IB tiles each) and addressing;
+//  streaming kernel: Z and Z' tiles, two slabs of C and of V in flight.
 template <typename T>
-constexpr int larfb_regs(int KT, int IB) {
+constexpr int larfb_reg_regs(int KT, int IB, int NW) {
+  return (larfb_spw(KT * 16, NW) * 4 * (IB + KT) + 8 * KT * IB + 48) * (int)(sizeof(T) / 4);
+}
+template <typename T>
+constexpr int larfb_stream_regs(int KT, int IB) {
   return (2 * KT * IB * 4 + 3 * IB * 4 + 2 * KT * 4 + 48) * (int)(sizeof(T) / 4);
 }
-constexpr int larfb_budget(int NW) { return NW >= 16 ? 96 : (NW >= 8 ? 176 : 256); }
+constexpr int larfb_reg_budget(int NW) { return NW >= 16 ? 128 : (NW >= 8 ? 240 : 0); }
+constexpr int larfb_stream_budget(int NW) { return NW >= 16 ? 96 : (NW >= 8 ? 176 : 256); }
 // LDS: NW partial Z tiles plus Z' (each KT*16 x IB*16).
 template <typename T>
 constexpr size_t larfb_lds(int KT, int IB, int NW) {
   return (size_t)(NW + 1) * (KT * 16) * (IB * 16) * sizeof(T);
 }
 template <typename T>
-constexpr bool larfb_valid(int KT, int IB, int NW) {
-  return larfb_regs<T>(KT, IB) <= larfb_budget(NW) && !(sizeof(T) == 8 && KT > 4) &&
+constexpr bool larfb_reg_valid(int KT, int IB, int NW) {
+  return larfb_reg_regs<T>(KT, IB, NW) <= larfb_reg_budget(NW) && larfb_lds<T>(KT, IB, NW) <= 128 * 1024;
+}
+template <typename T>
+constexpr bool larfb_stream_valid(int KT, int IB, int NW) {
+  return larfb_stream_regs<T>(KT, IB) <= larfb_stream_budget(NW) && !(sizeof(T) == 8 && KT > 4) &&
          larfb_lds<T>(KT, IB, NW) <= 128 * 1024;
+}
+template <typename T>
+constexpr bool larfb_valid(int KT, int IB, int NW) {
+  return larfb_reg_valid<T>(KT, IB, NW) || larfb_stream_valid<T>(KT, IB, NW);
 }
 
 // Fill kernels (used instead of hipMemsetAsync so that every step can be captured in a graph).

@@ -103,9 +103,23 @@ struct Level {
   int64_t chunk_rows;  // rows per chunk
   int32_t P;           // chunks
   RowMap rm;
+  int64_t ldv;         // leading dimension of this level's V (h rounded up to 16)
   int64_t voff;        // offset (elements) of this level's V in the V workspace
   int64_t toff;        // offset (elements) of this level's T factors
 };
+
+// 4-row vector access in the trailing update: float, rows contiguous, and every
+// 4-row group of C and of V starting on a 16-byte boundary.
+template <typename T>
+int larfb_vec_ok(const LarfbArgs<T>& a) {
+  if (sizeof(T) != 4 || a.M.rs != 1) return 0;
+  const RowMap& r = a.rm;
+  const bool rows4 = r.base % 4 == 0 && r.chunk_stride % 4 == 0 && (r.per_unit == 0 || (r.per_unit % 4 == 0 &&
+                                                                                          r.unit_stride % 4 == 0));
+  const bool mat4 = (reinterpret_cast<uintptr_t>(a.M.p) % 16) == 0 && a.M.cs % 4 == 0;
+  const bool v4 = (reinterpret_cast<uintptr_t>(a.V) % 16) == 0 && a.ldv % 4 == 0 && a.chunk_rows % 4 == 0;
+  return rows4 && mat4 && v4 ? 1 : 0;
+}
 
 std::vector<Level> plan_panel(int64_t r0, int64_t h, int bw, int tile, int hmax) {
   std::vector<Level> L;
@@ -125,9 +139,10 @@ std::vector<Level> plan_panel(int64_t r0, int64_t h, int bw, int tile, int hmax)
   l1.chunk_rows = cr;
   l1.P = (int32_t)P;
   l1.rm = RowMap{r0, cr, 0, 0};
+  l1.ldv = (h + 15) / 16 * 16;
   l1.voff = voff;
   l1.toff = toff;
-  voff += h * tile;
+  voff += l1.ldv * tile;
   toff += P * (int64_t)tile * tile;
   L.push_back(l1);
   int64_t U = cr;  // matrix rows between consecutive chunk tops of the previous level
@@ -145,9 +160,10 @@ std::vector<Level> plan_panel(int64_t r0, int64_t h, int bw, int tile, int hmax)
       lv.chunk_rows = F * bw;
       lv.rm = RowMap{r0, F * U, U, bw};
     }
+    lv.ldv = (lv.h + 15) / 16 * 16;
     lv.voff = voff;
     lv.toff = toff;
-    voff += lv.h * tile;
+    voff += lv.ldv * tile;
     toff += (int64_t)lv.P * tile * tile;
     L.push_back(lv);
     U = (lv.P > 1) ? F * U : U;
@@ -159,7 +175,7 @@ void panel_ws(int64_t h, int bw, int tile, int hmax, int64_t* vsz, int64_t* tsz)
   auto L = plan_panel(0, h, bw, tile, hmax);
   int64_t v = 0, t = 0;
   for (auto& l : L) {
-    v += l.h * tile;
+    v += l.ldv * tile;
     t += (int64_t)l.P * tile * tile;
   }
   *vsz = v;
@@ -263,7 +279,7 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
     a.chunk_rows = lv.chunk_rows;
     a.P = lv.P;
     a.V = vws + lv.voff;
-    a.ldv = lv.h;
+    a.ldv = lv.ldv;
     a.Tm = tws + lv.toff;
     HIPCHK(launch_chunk_qr<T>(cfg.tile, a, st));
   }
@@ -278,10 +294,11 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
       a.col0 = pc + bw;
       a.col1 = ncols;
       a.V = vws + lv.voff;
-      a.ldv = lv.h;
+      a.ldv = lv.ldv;
       a.Tm = tws + lv.toff;
       a.ldt = cfg.tile;
       a.k = (int32_t)(lv.P == 1 ? std::min<int64_t>(bw, lv.h) : bw);
+      a.vec = larfb_vec_ok(a);
       HIPCHK(launch_larfb<T>(cfg.tile, cfg.threads / 64, cfg.inner_block, a, st));
     }
   }
@@ -526,6 +543,11 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
   int rc = check_config_impl(h, w, dtype, c);
   if (rc) return rc;
   if (k > c.tile) return fail(SVDV_ERR_UNSUPPORTED, "k exceeds cfg->tile");
+  const bool tall_ok = dtype == SVDV_F32 ? larfb_stream_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
+                                          : larfb_stream_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
+  if (vrows > 32768 / c.tile && !tall_ok)
+    return fail(SVDV_ERR_UNSUPPORTED, "reflector length exceeds 32768 / cfg->tile, which this configuration "
+                                      "(threads, inner_block) only handles in registers");
   hipStream_t st = (hipStream_t)stream;
   auto run = [&](auto* Cp, auto* Vp, auto* Tp) -> int {
     typedef std::remove_pointer_t<decltype(Cp)> T;
@@ -542,6 +564,7 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
     a.Tm = Tp;
     a.ldt = ldt;
     a.k = (int32_t)k;
+    a.vec = larfb_vec_ok(a);
     HIPCHK(launch_larfb<T>(c.tile, c.threads / 64, c.inner_block, a, st));
     return SVDV_OK;
   };

@@ -1,18 +1,23 @@
 // Stage-1 trailing update, the operation the paper's Algorithm 2 performs and
 // auto-tunes: apply the orthogonal factor of a panel to the trailing matrix.
 // Here it is done in compact-WY form, C <- (I - V T V^T)^T C = C - V (T^T (V^T C)),
-// one TSQR chunk (rows of V) and one 16*IB-column tile of C per workgroup:
+// one TSQR chunk (rows of V) and one 16*IB-column strip of C per workgroup.
 //
-//   pass 1  Z = V^T C        the NW waves split the chunk's 16-row slabs; every
-//                            wave accumulates a partial Z on the MFMA units,
-//                            prefetching the next slab while it multiplies;
+// The strip stays in registers between the two products, so C crosses HBM
+// once each way:
+//
+//   load    the NW waves take the chunk's 16-row slabs round-robin (SPW slabs
+//           each) and issue every load of their slabs at once; with rows
+//           contiguous in memory (QR sweep) each lane loads 4 consecutive rows
+//           of one column as one 16-byte access;
+//   pass 1  Z = V^T C on the MFMA units, a partial Z per wave;
 //   reduce  Z = sum of the NW partials in LDS (fixed order: deterministic);
-//   small   Z' = T^T Z       (vector FMAs, from LDS);
-//   pass 2  C -= V Z'        again slab-parallel over the waves, MFMA, with the
-//                            next slab prefetched.
+//   small   Z' = T^T Z (vector FMAs, from LDS);
+//   pass 2  C -= V Z' on the MFMA units, accumulating into the C registers,
+//           which are then stored.
 //
 // The paper's tunables map onto this kernel as: threads = NW * 64 (waves that
-// share a column tile and split its rows, like the split-K "K" of Algorithm 2),
+// share a column strip and split its rows, like the split-K "K" of Algorithm 2),
 // inner_block = IB (16-column MFMA tiles per workgroup, like "CPB").
 #include <algorithm>
 #include "common.hpp"
@@ -20,6 +25,198 @@
 
 namespace svdv {
 
+// MFMA operand layout used throughout (16x16x4): lane (g, nl) = (lane / 16, lane % 16).
+// The C registers of a slab hold rows acc_row<T>(g, i), i = 0..3, of column nl: the
+// K index of pass 1 and the output rows of pass 2 use the same assignment, so the
+// pass-2 accumulator starts from, and ends in, the registers that were loaded.
+
+// Loads rows q0 + acc_row(g, i) (i = 0..3) of view column `col` (zero outside the
+// chunk or the strip).
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_c(const LarfbArgs<T>& a, int c, int Hc, int q0, int g, int64_t col, T (&x)[4]) {
+  const bool cok = col < a.col1;
+  if constexpr (VEC) {
+    // float, rows contiguous: rows q0+4g .. q0+4g+3 are consecutive in memory
+    const int qa = q0 + 4 * g;
+    if (cok && qa + 3 < Hc) {
+      const float4 v = *reinterpret_cast<const float4*>(&a.M.at(a.rm.row(c, qa), col));
+      x[0] = v.x;
+      x[1] = v.y;
+      x[2] = v.z;
+      x[3] = v.w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + acc_row<T>(g, i);
+    x[i] = (cok && q < Hc) ? a.M.at(a.rm.row(c, q), col) : T(0);
+  }
+}
+
+template <typename T, bool VEC>
+__device__ __forceinline__ void store_c(const LarfbArgs<T>& a, int c, int Hc, int q0, int g, int64_t col,
+                                        const typename Acc<T>::type& x) {
+  if (col >= a.col1) return;
+  if constexpr (VEC) {
+    const int qa = q0 + 4 * g;
+    if (qa + 3 < Hc) {
+      *reinterpret_cast<float4*>(&a.M.at(a.rm.row(c, qa), col)) = float4{x[0], x[1], x[2], x[3]};
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + acc_row<T>(g, i);
+    if (q < Hc) a.M.at(a.rm.row(c, q), col) = x[i];
+  }
+}
+
+// Pass-1 operand: V^T rows (reflector r = 16 mt + nl), K = rows q0 + acc_row(g, i).
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int Hc, int q0, int g, int r, T (&x)[4]) {
+  const bool rok = r < a.k;
+  if constexpr (VEC) {
+    const int qa = q0 + 4 * g;
+    if (rok && qa + 3 < Hc) {
+      const float4 v = *reinterpret_cast<const float4*>(V + qa + (int64_t)r * a.ldv);
+      x[0] = v.x;
+      x[1] = v.y;
+      x[2] = v.z;
+      x[3] = v.w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + acc_row<T>(g, i);
+    x[i] = (rok && q < Hc) ? V[q + (int64_t)r * a.ldv] : T(0);
+  }
+}
+
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC>
+__global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
+  typedef typename Acc<T>::type AccT;
+  constexpr int KR = KT * 16, CB = IB * 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Zs = reinterpret_cast<T*>(smem_raw);  // [NW][KR][CB] partial sums; slot 0 then holds Z
+  T* Zp = Zs + (size_t)NW * KR * CB;       // [KR][CB] Z' = T^T Z
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, nl = lane & 15;
+  const int c = blockIdx.y;
+  const int64_t row0 = (int64_t)c * a.chunk_rows;
+  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
+  const int k = a.k;
+  const int64_t colbase = a.col0 + (int64_t)blockIdx.x * CB;
+  const T* V = a.V + row0;
+  const T* Tm = a.Tm + (int64_t)c * a.ldt * a.ldt;
+  const int nslab = (Hc + 15) >> 4;
+
+  // ---------------- load the strip and the pass-1 operands ----------------
+  T cr[SPW][IB][4];
+  T vr[SPW][KT][4];
+#pragma unroll
+  for (int j = 0; j < SPW; ++j) {
+    const int s = wv + j * NW;
+    const int q0 = s * 16;
+    if (s < nslab) {
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cr[j][nt][i] = T(0);
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vr[j][mt][i] = T(0);
+    }
+  }
+
+  // ---------------- pass 1: partial Z = V^T C ----------------
+  AccT Z[KT][IB];
+#pragma unroll
+  for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < SPW; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[j][mt][i], cr[j][nt][i], Z[mt][nt]);
+
+  // pass-2 operands (reflectors along K, rows along lanes), requested before the reduction
+  // A[m = row][k = reflector]: lane (g, nl) holds -V[q0 + nl][4 kk + g], kk = 0..KR/4-1
+  T va[SPW][KR / 4];
+#pragma unroll
+  for (int j = 0; j < SPW; ++j) {
+    const int q = (wv + j * NW) * 16 + nl;
+#pragma unroll
+    for (int kk = 0; kk < KR / 4; ++kk) {
+      const int r = 4 * kk + g;
+      va[j][kk] = (q < Hc && r < k) ? -V[q + (int64_t)r * a.ldv] : T(0);
+    }
+  }
+
+  // ---------------- reduce the NW partials (fixed order) ----------------
+  {
+    T* mine = Zs + (size_t)wv * KR * CB;
+#pragma unroll
+    for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mine[(mt * 16 + acc_row<T>(g, r)) * CB + nt * 16 + nl] = Z[mt][nt][r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+    T acc = Zs[e];
+    for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
+    Zs[e] = acc;
+  }
+  __syncthreads();
+  // ---------------- Z' = T^T Z (T upper triangular, k x k) ----------------
+  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+    const int i = e / CB, col = e - i * CB;
+    T acc = T(0);
+    if (i < k)
+      for (int l = 0; l <= i; ++l) acc += Tm[l + (int64_t)i * a.ldt] * Zs[l * CB + col];
+    Zp[e] = acc;
+  }
+  __syncthreads();
+
+  // ---------------- pass 2: C -= V Z', accumulated into the strip registers ----------------
+  // B[k = reflector][n = column]: lane (g, nl) holds Z'[4 kk + g][16 nt + nl]
+  T zb[KR / 4][IB];
+#pragma unroll
+  for (int kk = 0; kk < KR / 4; ++kk)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) zb[kk][nt] = Zp[(4 * kk + g) * CB + nt * 16 + nl];
+#pragma unroll
+  for (int j = 0; j < SPW; ++j) {
+    const int s = wv + j * NW;
+    if (s >= nslab) break;
+    AccT acc[IB];
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) acc[nt] = AccT{cr[j][nt][0], cr[j][nt][1], cr[j][nt][2], cr[j][nt][3]};
+#pragma unroll
+    for (int kk = 0; kk < KR / 4; ++kk)
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) acc[nt] = mfma16(va[j][kk], zb[kk][nt], acc[nt]);
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) store_c<T, VEC>(a, c, Hc, s * 16, g, colbase + nt * 16 + nl, acc[nt]);
+  }
+}
+
+// Streaming variant, for strips that do not fit in registers: C is read in
+// pass 1, read again and written in pass 2, with the next 16-row slab of each
+// wave prefetched while the current one is multiplied.
 template <typename T, int KT, int IB>
 __device__ __forceinline__ void load_slab1(const LarfbArgs<T>& a, const T* V, int c, int Hc, int64_t colbase, int s,
                                            int g, int nl, T (&cb)[IB][4], T (&av)[KT][4]) {
@@ -67,7 +264,7 @@ __device__ __forceinline__ void load_slab2(const LarfbArgs<T>& a, const T* V, in
 }
 
 template <typename T, int KT, int IB, int NW>
-__global__ void __launch_bounds__(NW * 64) k_larfb(LarfbArgs<T> a) {
+__global__ void __launch_bounds__(NW * 64) k_larfb_stream(LarfbArgs<T> a) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -183,23 +380,56 @@ __global__ void __launch_bounds__(NW * 64) k_larfb(LarfbArgs<T> a) {
   }
 }
 
+template <typename T, int KT, int IB, int NW, bool VEC>
+static hipError_t launch_larfb_reg(const LarfbArgs<T>& a, hipStream_t st) {
+  constexpr int SPW = larfb_spw(KT * 16, NW);
+  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg<T, KT, IB, NW, SPW, VEC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  const int64_t ncols = a.col1 - a.col0;
+  const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), (unsigned)a.P);
+  hipLaunchKernelGGL((k_larfb_reg<T, KT, IB, NW, SPW, VEC>), grid, dim3(NW * 64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int KT, int IB, int NW>
+static hipError_t launch_larfb_stream(const LarfbArgs<T>& a, hipStream_t st) {
+  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_stream<T, KT, IB, NW>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  const int64_t ncols = a.col1 - a.col0;
+  const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), (unsigned)a.P);
+  hipLaunchKernelGGL((k_larfb_stream<T, KT, IB, NW>), grid, dim3(NW * 64), lds, st, a);
+  return hipGetLastError();
+}
+
 template <typename T, int KT, int IB, int NW>
 static hipError_t launch_larfb_nw(const LarfbArgs<T>& a, hipStream_t st) {
-  if constexpr (larfb_valid<T>(KT, IB, NW)) {
-    constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
-    static bool configured = false;
-    if (!configured) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_larfb<T, KT, IB, NW>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      configured = true;
+  // the register-strip kernel when the chunk fits in its registers, else the streaming one
+  const int64_t cap = (int64_t)larfb_spw(KT * 16, NW) * NW * 16;
+  const bool fits = a.chunk_rows <= cap && a.h - (int64_t)(a.P - 1) * a.chunk_rows <= cap;
+  if constexpr (larfb_reg_valid<T>(KT, IB, NW)) {
+    if (fits) {
+      if constexpr (sizeof(T) == 4) {
+        if (a.vec) return launch_larfb_reg<T, KT, IB, NW, true>(a, st);
+      }
+      return launch_larfb_reg<T, KT, IB, NW, false>(a, st);
     }
-    const int64_t ncols = a.col1 - a.col0;
-    const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), (unsigned)a.P);
-    hipLaunchKernelGGL((k_larfb<T, KT, IB, NW>), grid, dim3(NW * 64), lds, st, a);
-    return hipGetLastError();
+  }
+  if constexpr (larfb_stream_valid<T>(KT, IB, NW)) {
+    return launch_larfb_stream<T, KT, IB, NW>(a, st);
   } else {
-    return hipErrorInvalidConfiguration;
+    return hipErrorInvalidValue;
   }
 }
 

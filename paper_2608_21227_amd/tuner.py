@@ -168,3 +168,60 @@ def lookup(table: dict, n: int, dtype: str) -> Config | None:
 def lookup_median(table: dict, n: int, dtype: str) -> Config | None:
     e = _entry(table, n, dtype)
     return Config(**e["median"]) if e else None
+
+
+# --------------------------------------------------------------------------- command line
+
+def main(argv=None) -> None:
+    """python -m paper_2608_21227_amd.tuner --n 4096 --dtype float32 [--reps 5] [--db PATH] [--limit K]
+
+    Measures the whole space at one (n, dtype) cell on the current GPU (resuming
+    from the database), prints the summary and records best and median in the
+    tuned table."""
+    import argparse
+    import sys
+    import numpy as np
+    import torch
+    from . import default_config
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--db", default=None)
+    ap.add_argument("--table", default=TABLE_PATH)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--time-budget", type=float, default=0.0, help="stop measuring after this many seconds")
+    args = ap.parse_args(argv)
+    n, dtype = args.n, args.dtype
+    db = args.db or os.path.join(_HERE, f"tuning_{n}_{dtype}.jsonl")
+    rng = np.random.default_rng(np.random.SeedSequence(260821227, spawn_key=(1, n, 0 if dtype == "float32" else 1)))
+    a_np = rng.standard_normal((n, n)).astype(dtype)
+    a = torch.from_numpy(np.ascontiguousarray(a_np.T)).t().cuda()
+    t0 = time.time()
+    cfgs = space()
+    order = np.random.default_rng(args.seed).permutation(len(cfgs))  # interleave so a partial run is a fair sample
+    cfgs = [cfgs[i] for i in order]
+
+    def measure(cfg):
+        if args.time_budget and time.time() - t0 > args.time_budget:
+            raise TimeoutError
+        return measure_fn(a, cfg, args.reps)
+
+    try:
+        recs = tune(n, dtype, cfgs, db, measure, progress=lambda m: print("[tune]", m, flush=True))
+    except TimeoutError:
+        print("[tune] time budget reached; partial database kept", flush=True)
+        recs = [r for r in read_db(db) if r.get("n") == n and r.get("dtype") == dtype]
+    summ = summarize(recs)
+    summ["plain_ms"] = next((r["median_ms"] for r in recs if r.get("key") == key_of(PLAIN) and r.get("status") == "ok"), None)
+    summ["default"] = default_config(n, n, dtype).as_dict()
+    print(json.dumps(summ), flush=True)
+    if summ.get("valid"):
+        table = load_table(args.table)
+        table[f"{n}_{dtype}"] = {k: summ[k] for k in ("best", "best_ms", "median", "median_ms", "valid", "invalid",
+                                                      "ratio_median_over_best", "plain_ms")}
+        save_table(table, args.table)
+
+
+if __name__ == "__main__":
+    main()
