@@ -60,16 +60,45 @@ def time_config(a, cfg, steps: int, warmup: int, torch):
 
 
 def stage_breakdown(a, cfg, reps: int, torch):
+    """Median per-stage times and per-kernel-class statistics of `reps` timed calls."""
+    acc, kacc = {}, {"update": [], "panel": []}
     svdv.set_timing(True)
-    acc = {}
     for _ in range(reps):
         svdv.svd_values(a, config=cfg)
-        t = svdv.last_timing()
-        for k, v in t.items():
+        for k, v in svdv.last_timing().items():
             acc.setdefault(k, []).append(v)
+    # kernel-class statistics in separate calls (their per-launch events lengthen stage 1)
+    svdv.set_timing(True, kernels=True)
+    for _ in range(reps):
+        svdv.svd_values(a, config=cfg)
+        for kind in kacc:
+            kacc[kind].append(svdv.last_kernel_stats(kind))
     svdv.set_timing(False)
     torch.cuda.synchronize()
-    return {k: float(np.median(v)) for k, v in acc.items()}
+    kstats = {}
+    for kind, lst in kacc.items():
+        med = sorted(lst, key=lambda r: r["ms"])[len(lst) // 2]
+        kstats[kind] = med
+    return {k: float(np.median(v)) for k, v in acc.items()}, kstats
+
+
+def traffic_for(kind: str, cfg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken for this kernel class and configuration with the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    e = rec.get(kind)
+    if not e or e.get("config") != cfg.as_dict():
+        return None
+    src = os.path.join(ROOT, "paper_2608_21227_amd", "csrc", e["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e.get("source_sha256"):
+            return None  # the kernel changed since the counters were taken
+    return e.get("bytes_per_launch")
 
 
 def cpu_baseline(a_np: np.ndarray, n: int, sweeps_total: int):
@@ -119,7 +148,7 @@ def main():
         if name == "tuned":
             s_tuned = s.cpu().numpy().astype(np.float64)
     print("[bench] stage breakdown", file=sys.stderr, flush=True)
-    stages = stage_breakdown(a, tuned, 3, torch)
+    stages, kstats = stage_breakdown(a, tuned, 3, torch)
 
     # parity spot check against the stored oracle values (full size)
     gold = os.path.join(ROOT, "tests", "golden", f"cfg1_n{n}_{dtype}.npy")
@@ -129,16 +158,40 @@ def main():
         diff = np.abs(s_tuned - ref)
         parity = {"normwise": float(diff.max() / ref[0]), "max_rel": float(np.max(diff / ref))}
 
-    # roofline of the dominant kernel: the bulge chase (one launch per call)
+    # roofline of each hot kernel class, measured live (events on the library's stream)
     b = tuned.tile
-    fl = chase_flops(n, b)
+    es = 4 if dtype == "float32" else 8
+    ridge = (PEAKS["fp32_TF"] if dtype == "float32" else PEAKS["fp64_TF"]) * 1e12 / (PEAKS["hbm_GBs"] * 1e9)
+    kinds = {}
     t_chase = stages.get("chase", float("nan")) * 1e-3
-    achieved = fl / t_chase / 1e12
+    fl = chase_flops(n, b)
+    kinds["chase"] = {"kernel": "k_chase_* (stage 2 bulge chase, float64; one launch per call)", "launches": 1,
+                      "ms": t_chase * 1e3, "bound": "alu", "achieved": fl / t_chase / 1e12,
+                      "peak": PEAKS["fp64_vec_TF"], "unit": "TFLOP/s", "flops_per_launch": fl}
+    for kind, name in (("update", "k_larfb_* (stage 1 trailing update, Algorithm 2's operation)"),
+                       ("panel", "k_chunk_qr (stage 1 panel QR/LQ)")):
+        ks = kstats[kind]
+        t = ks["ms"] * 1e-3
+        if not ks["launches"] or t <= 0:
+            continue
+        inten = ks["flops"] / ks["bytes"]
+        if kind == "update" and inten >= ridge:
+            ach, peak, unit, bound = ks["flops"] / t / 1e12, (PEAKS["fp32_TF"] if dtype == "float32" else PEAKS["fp64_TF"]), "TFLOP/s", "mfma"
+        else:
+            ach, peak, unit, bound = ks["bytes"] / t / 1e9, PEAKS["hbm_GBs"], "GB/s", "hbm"
+        kinds[kind] = {"kernel": name, "launches": ks["launches"], "ms": ks["ms"], "bound": bound, "achieved": ach,
+                       "peak": peak, "unit": unit, "avg_launch_us": 1e3 * ks["ms"] / ks["launches"],
+                       "alg_flops": ks["flops"], "alg_bytes": ks["bytes"]}
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    rooflines = {}
+    for k, v in kinds.items():
+        rooflines[k] = {"bound": v["bound"], "achieved": round(v["achieved"], 6), "peak": v["peak"], "unit": v["unit"],
+                        "frac": round(v["achieved"] / v["peak"], 6), "ms_per_step": round(v["ms"], 4),
+                        "launches_per_step": v["launches"], "kernel": v["kernel"]}
+    roofline = dict(rooflines[dom])
+    roofline["traffic"] = traffic_for(dom, tuned)
     t_stage1 = stages.get("stage1", float("nan")) * 1e-3
     s1_flops = 8.0 / 3.0 * n ** 3
-    roofline = {"bound": "alu", "kernel": "k_chase (stage 2 bulge chase, float64)", "achieved": round(achieved, 5),
-                "peak": PEAKS["fp64_vec_TF"], "unit": "TFLOP/s", "frac": round(achieved / PEAKS["fp64_vec_TF"], 6),
-                "traffic": None, "flops_per_launch": fl}
 
     tuned_ms = res["tuned"]["ms"]
     out = {
@@ -165,6 +218,7 @@ def main():
                                           4 * (4 if dtype == "float32" else 8) * n ** 3 / (3 * b) / (PEAKS["hbm_GBs"] * 1e9))
                                       / t_stage1, 5),
         "roofline": roofline,
+        "rooflines": rooflines,
         "parity_vs_oracle": parity,
     }
     if not args.no_cpu:

@@ -163,9 +163,23 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* 
  * bulge-chase kernel, [4] the bisection kernels.  svdv_last_timing waits for
  * the last call's events and writes up to n elapsed times in milliseconds
  * (HOST array) followed by [5] the whole call; returns the count written.
+ * svdv_timing(2) in addition brackets every stage-1 kernel launch with an event
+ * pair (for svdv_last_kernel_stats; the extra events lengthen stage 1);
+ * svdv_timing(0) switches timing off.
  */
 int svdv_timing(int enable);
 int svdv_last_timing(double* ms, int n);
+/*
+ * svdv_last_kernel_stats: per kernel class of the last timed call (kind 0: the
+ * stage-1 trailing update, Algorithm 2's operation; kind 1: the stage-1 panel
+ * factorisation), writes to the HOST array out[0..3]: number of launches, sum
+ * of their event-timed durations in milliseconds, algorithmic flops and
+ * algorithmic bytes (trailing update of an r x w block with k reflectors:
+ * 4 r w k flops, (2 r w + r k) elements; panel of r x b: 2 r b^2 flops, 2 r b
+ * elements).  Requires svdv_timing(2) before the call.  Returns 4, or an error
+ * status (n < 4, bad kind, no timed call).
+ */
+int svdv_last_kernel_stats(int kind, double* out, int n);
 
 /* Text for a status code (static string). */
 const char* svdv_status_string(int status);

@@ -22,7 +22,8 @@ STATUS = {0: "SVDV_OK", -1: "SVDV_ERR_INVALID_ARG", -2: "SVDV_ERR_UNSUPPORTED", 
 # Every symbol include/svdv.h declares (checked by the CPU test-suite).
 EXPORTS = ["svd_values", "svd_values_ex", "svd_values_batched", "svdv_default_config", "svdv_check_config",
            "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
-           "svdv_last_error", "svdv_release", "svdv_timing", "svdv_last_timing"]
+           "svdv_last_error", "svdv_release", "svdv_timing", "svdv_last_timing",
+           "svdv_last_kernel_stats"]
 
 
 class SvdvError(RuntimeError):
@@ -80,6 +81,7 @@ def lib():
             "svdv_release": [],
             "svdv_timing": [ctypes.c_int],
             "svdv_last_timing": [ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+            "svdv_last_kernel_stats": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -258,9 +260,10 @@ def apply_qt(V, T, C, side: int = 0, config=None):
 STAGES = ["stage_in", "stage1", "band_pack", "chase", "bisect", "total"]
 
 
-def set_timing(enable: bool):
-    """Record per-stage HIP events in later calls on this thread (instrumentation)."""
-    _check(lib().svdv_timing(1 if enable else 0))
+def set_timing(enable, kernels: bool = False):
+    """Record per-stage HIP events in later calls on this thread (instrumentation);
+    with kernels=True also bracket every stage-1 launch (see last_kernel_stats)."""
+    _check(lib().svdv_timing((2 if kernels else 1) if enable else 0))
 
 
 def last_timing() -> dict:
@@ -270,6 +273,14 @@ def last_timing() -> dict:
     if k < 0:
         _check(k)
     return {name: buf[i] for i, name in enumerate(STAGES[:k])}
+
+
+def last_kernel_stats(kind: str) -> dict:
+    """Launch count, summed event time (ms) and algorithmic flops / bytes of one
+    kernel class ("update" or "panel") in the last timed call."""
+    buf = (ctypes.c_double * 4)()
+    _check(min(0, lib().svdv_last_kernel_stats({"update": 0, "panel": 1}[kind], buf, 4)))
+    return {"launches": int(buf[0]), "ms": buf[1], "flops": buf[2], "bytes": buf[3]}
 
 
 def release():

@@ -8,8 +8,11 @@
 namespace svdv {
 
 // Rows per lane of the chunk-QR kernel (16 waves, one chunk in registers):
-// 64 * RPT rows * TILE columns = 32 elements per thread.
-template <int TILE> struct ChunkRPT { static constexpr int value = 512 / TILE; };
+// 64 * RPT rows * TILE columns = 32 elements per thread (16 for float64 at
+// tile 16, whose single column per wave would otherwise not fit in registers).
+template <typename T, int TILE> struct ChunkRPT {
+  static constexpr int value = (sizeof(T) == 8 && TILE == 16 ? 256 : 512) / TILE;
+};
 
 template <typename T>
 struct ChunkQRArgs {
@@ -42,7 +45,7 @@ struct LarfbArgs {
 };
 
 // Slabs (16 rows) per wave of the trailing update: enough for the largest chunk a
-// panel level can have (the chunk-QR capacity, 32768 / tile rows).
+// panel level can have (at most the chunk-QR capacity, 32768 / tile rows).
 constexpr int larfb_spw(int tile, int NW) { return ((32768 / tile + 15) / 16 + NW - 1) / NW; }
 // Register estimates (32-bit registers per lane), calibrated against the
 // compiler's resource report so that no configuration taken spills to scratch.
@@ -100,6 +103,7 @@ hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, d
 // Stage 2.
 struct ChaseArgs {
   double* Bs;          // chase storage, row-major, row i at Bs + i*ldb; column j at offset j - i + (b-1)
+                       // (ldb = 3b: the windowed kernels rely on it)
   int64_t ldb;
   int64_t n;
   int32_t b;
@@ -110,9 +114,7 @@ struct ChaseArgs {
   int32_t* err;        // set when a bounded wait gives up
   double* d;
   double* e;
-  double* dummy;       // per-thread dummy store targets of the pipelined kernel (kChaseDummy doubles)
 };
-constexpr int64_t kChaseDummy = 2048 * 384;
 size_t chase_lds_bytes(int b, int W);
 int chase_max_groups_resident(int b, int W);
 hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st);

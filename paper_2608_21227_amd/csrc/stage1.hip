@@ -99,6 +99,9 @@ struct ChunkQRCfg {
   static constexpr int NW = 16;
   static constexpr int CPT = TILE / NW;
   static constexpr int HMAX = 64 * RPT;
+  // 64-row blocks transposed per barrier pair when loading (stage area <= 64 KiB)
+  static constexpr int CQB0 = (64 * 1024) / (64 * (TILE + 1) * (int)sizeof(T));
+  static constexpr int CQB = CQB0 >= RPT ? RPT : (CQB0 >= 8 ? 8 : (CQB0 >= 4 ? 4 : (CQB0 >= 2 ? 2 : 1)));
 };
 
 template <typename T, int TILE, int RPT>
@@ -113,41 +116,61 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
   const int kr = Hc < bw ? Hc : bw;
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // LDS: stage tile [64][TILE+1] (also reused as Mtmp at the end) | vbuf[2][HMAX] | taus[TILE] | Tl[TILE][TILE+1]
+  // LDS: stage [CQB*64][TILE+1] (also reused as Mtmp at the end) | vbuf[2][HMAX] | taus[TILE] | Tl[TILE][TILE+1]
   T* stage = reinterpret_cast<T*>(smem_raw);
   T* Mtmp = stage;
-  T* vbuf = stage + 64 * (TILE + 1);
+  T* vbuf = stage + C::CQB * 64 * (TILE + 1);
   T* taus = vbuf + 2 * C::HMAX;
   T* Tl = taus + TILE;
   constexpr int LDT = TILE + 1;
 
   T x[RPT][CPT];
 
-  // ---- load the chunk through LDS (coalesced along the memory-contiguous direction) ----
-  const bool rows_contig = (a.M.rs == 1);
-  for (int i = 0; i < RPT; ++i) {
-    const int qb = i * 64;
-    if (qb >= Hc) {  // uniform
-#pragma unroll
-      for (int cc = 0; cc < CPT; ++cc) x[i][cc] = T(0);
-      continue;
+  // ---- load the chunk, with the global loads issued in bursts ----
+  // rows contiguous (QR sweep): lane l reads rows i*64+l of its columns directly
+  // (coalesced along rows).  Otherwise (LQ sweep) threads read along the
+  // memory-contiguous columns and the blocks are transposed through LDS, CQB
+  // 64-row blocks (loaded together) per barrier pair.
+  auto fetch = [&](int q, int col) -> T {
+    T v = T(0);
+    if (q < Hc && col < bw) {
+      v = a.M.at(a.rm.row(c, q), a.pc + col);
+      if (a.rm.per_unit != 0 && (q % a.rm.per_unit) > col) v = T(0);
     }
-    for (int t = threadIdx.x; t < 64 * TILE; t += 1024) {
-      int r, col;
-      if (rows_contig) { col = t >> 6; r = t & 63; } else { r = t / TILE; col = t - r * TILE; }
-      const int q = qb + r;
-      T v = T(0);
-      if (q < Hc && col < bw) {
-        const int64_t gr = a.rm.row(c, q);
-        v = a.M.at(gr, a.pc + col);
-        if (a.rm.per_unit != 0 && (q % a.rm.per_unit) > col) v = T(0);
-      }
-      stage[r * (TILE + 1) + col] = v;
-    }
-    __syncthreads();
+    return v;
+  };
+  if (a.M.rs == 1) {
 #pragma unroll
-    for (int cc = 0; cc < CPT; ++cc) x[i][cc] = stage[l * (TILE + 1) + w * CPT + cc];
-    __syncthreads();
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+      for (int cc = 0; cc < CPT; ++cc) x[i][cc] = fetch(i * 64 + l, w * CPT + cc);
+  } else {
+    constexpr int EPT = TILE / 16;  // elements of one 64 x TILE block per thread
+    constexpr int CQB = C::CQB;
+#pragma unroll
+    for (int i0 = 0; i0 < RPT; i0 += CQB) {
+      T tmp[CQB][EPT];
+#pragma unroll
+      for (int ib = 0; ib < CQB; ++ib)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int t = threadIdx.x + k * 1024;
+          tmp[ib][k] = fetch((i0 + ib) * 64 + t / TILE, t % TILE);
+        }
+#pragma unroll
+      for (int ib = 0; ib < CQB; ++ib)
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int t = threadIdx.x + k * 1024;
+          stage[(ib * 64 + t / TILE) * (TILE + 1) + t % TILE] = tmp[ib][k];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int ib = 0; ib < CQB; ++ib)
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) x[i0 + ib][cc] = stage[(ib * 64 + l) * (TILE + 1) + w * CPT + cc];
+      __syncthreads();
+    }
   }
 
   // ---- Householder loop over the panel columns ----
@@ -155,17 +178,17 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
     const int ow = j / CPT, oc = j % CPT;
     T* vb = vbuf + (j & 1) * C::HMAX;
     if (w == ow) {
-      double ss = 0.0, alpha_l = 0.0;
+      double sp[4] = {0.0, 0.0, 0.0, 0.0}, alpha_l = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int q = i * 64 + l;
         double v = 0.0;
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) if (cc == oc) v = (double)x[i][cc];
-        if (q > j) ss += v * v;
+        if (q > j) sp[i & 3] += v * v;
         if (q == j) alpha_l = v;
       }
-      ss = wave_sum(ss);
+      const double ss = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
       const double alpha = __shfl(alpha_l, j & 63, kWave);
       double beta = alpha, tau = 0.0, scal = 0.0;
       if (ss > 0.0) {
@@ -193,21 +216,30 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
     }
     __syncthreads();
     const T tau = taus[j];
-    T vr[RPT];
+    // v is kept in registers when the chunk leaves room for it, else re-read from LDS
+    constexpr bool kCacheV = RPT * ((int)sizeof(T) / 4) * (CPT + 1) <= 96;
+    T vr[kCacheV ? RPT : 1];
+    if constexpr (kCacheV) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) vr[i] = vb[i * 64 + l];
+      for (int i = 0; i < RPT; ++i) vr[i] = vb[i * 64 + l];
+    }
+    auto vget = [&](int i) -> T {
+      if constexpr (kCacheV) return vr[i];
+      else return vb[i * 64 + l];
+    };
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
       const int gc = w * CPT + cc;
       if (gc == j || gc >= bw) continue;
-      T d = T(0);
+      // four independent partial sums shorten the dependent FMA chain
+      T dp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) d += vr[i] * x[i][cc];
-      d = wave_sum(d);
+      for (int i = 0; i < RPT; ++i) dp[i & 3] += vget(i) * x[i][cc];
+      T d = wave_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
       if (gc > j) {
         const T td = tau * d;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) x[i][cc] -= td * vr[i];
+        for (int i = 0; i < RPT; ++i) x[i][cc] -= td * vget(i);
       } else if (l == 0) {
         Tl[gc * LDT + j] = d;  // Y[gc][j] = v_gc^T v_j
       }
@@ -345,7 +377,7 @@ hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int tr
 
 template <typename T, int TILE, int RPT>
 static size_t chunk_qr_lds() {
-  return sizeof(T) * (64 * (TILE + 1) + 2 * 64 * RPT + TILE + TILE * (TILE + 1));
+  return sizeof(T) * (ChunkQRCfg<T, TILE, RPT>::CQB * 64 * (TILE + 1) + 2 * 64 * RPT + TILE + TILE * (TILE + 1));
 }
 
 template <typename T, int TILE, int RPT>
@@ -369,10 +401,10 @@ static hipError_t launch_cqr(const ChunkQRArgs<T>& a, hipStream_t st) {
 template <typename T>
 int chunk_qr_hmax(int tile) {
   switch (tile) {
-    case 16: return 64 * ChunkRPT<16>::value;
-    case 32: return 64 * ChunkRPT<32>::value;
-    case 64: return 64 * ChunkRPT<64>::value;
-    case 128: return 64 * ChunkRPT<128>::value;
+    case 16: return 64 * ChunkRPT<T, 16>::value;
+    case 32: return 64 * ChunkRPT<T, 32>::value;
+    case 64: return 64 * ChunkRPT<T, 64>::value;
+    case 128: return 64 * ChunkRPT<T, 128>::value;
   }
   return 0;
 }
@@ -382,10 +414,10 @@ template int chunk_qr_hmax<double>(int);
 template <typename T>
 hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st) {
   switch (tile) {
-    case 16: return launch_cqr<T, 16, ChunkRPT<16>::value>(a, st);
-    case 32: return launch_cqr<T, 32, ChunkRPT<32>::value>(a, st);
-    case 64: return launch_cqr<T, 64, ChunkRPT<64>::value>(a, st);
-    case 128: return launch_cqr<T, 128, ChunkRPT<128>::value>(a, st);
+    case 16: return launch_cqr<T, 16, ChunkRPT<T, 16>::value>(a, st);
+    case 32: return launch_cqr<T, 32, ChunkRPT<T, 32>::value>(a, st);
+    case 64: return launch_cqr<T, 64, ChunkRPT<T, 64>::value>(a, st);
+    case 128: return launch_cqr<T, 128, ChunkRPT<T, 128>::value>(a, st);
   }
   return hipErrorInvalidValue;
 }

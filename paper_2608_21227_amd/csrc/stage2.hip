@@ -33,16 +33,17 @@ namespace svdv {
 // eight timestamps per step of the 100 MHz real-time counter.
 #ifdef SVDV_CHASE_TRACE
 __device__ uint64_t g_chase_trace[8 * 1024];
-#define CHASE_MARK(gi, t, k)                                                   \
+#define CHASE_MARK_IF(cond, gi, t, k)                                          \
   do {                                                                         \
-    if ((gi) == 0 && threadIdx.x == 0 && (t) < 1024)                           \
+    if ((cond) && (gi) == 0 && (t) < 1024)                                     \
       g_chase_trace[(t) * 8 + (k)] = __builtin_amdgcn_s_memrealtime();         \
   } while (0)
 #else
-#define CHASE_MARK(gi, t, k) \
-  do {                       \
+#define CHASE_MARK_IF(cond, gi, t, k) \
+  do {                                \
   } while (0)
 #endif
+#define CHASE_MARK(gi, t, k) CHASE_MARK_IF(threadIdx.x == 0, gi, t, k)
 
 __device__ __forceinline__ double bld(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -309,7 +310,7 @@ __host__ __device__ inline int win_rows(int b, int W) { return (3 * W + 2) * b +
 
 size_t chase_win_lds_bytes(int b, int W) {
   if (b != 16 && b != 32) return (size_t)1 << 40;
-  return (size_t)(win_rows(b, W) + 1) * (3 * b + 2) * sizeof(double);  // ring + zero slot
+  return ((size_t)(win_rows(b, W) + 1) * (3 * b + 2) + (size_t)16 * b) * sizeof(double);  // ring + zero slot + reflector slots
 }
 
 // Ring slot of row r: (r - base) mod R (base <= every row the window holds;
@@ -344,19 +345,24 @@ __device__ __forceinline__ void wave_reflector(double x, int lane, int L, double
   v = lane < L ? (lane == 0 ? 1.0 : x * scal) : 0.0;
 }
 
-// One task (p, c) on the window, executed by one wave.  The reflector entries are
-// broadcast into scalar registers and every lane loads its whole row (right
-// update) or column (left update) into registers before using it, so each
-// update costs one round of LDS latency rather than one per entry.  The loops
-// run over all B entries whatever L is: the reflector is zero beyond L, the
-// right update then reads and rewrites band positions past column n (zeros),
-// and the left update reads rows past n from the zero slot `zs` (a slot kept at
-// zero), so no entry changes and no loop needs a branch.  The slot stride is
-// 3B+2: a column of the band walks the slots with stride 3B+1 (odd), which
-// spreads the lanes of the right update over distinct banks.
+// One task (p, c) on the window, executed by one wave.  Every lane loads its
+// whole row (right update) or column (left update) into registers before the
+// reflector is formed, so those loads overlap the reduction; the reflector
+// entries then go through the wave's LDS slot `vbw` (B doubles) and come back
+// to every lane as wide broadcast reads.  The loops run over all B entries
+// whatever L is: the reflector is zero beyond L, the right update then reads
+// and rewrites band positions past column n (zeros), and the left update reads
+// rows past n from the zero slot `zs` (a slot kept at zero), so no entry
+// changes and no loop needs a branch.  The slot stride is 3B+2: a column of the
+// band walks the slots with stride 3B+1 (odd), which spreads the lanes of the
+// right update over distinct banks.  LDS operations of one wave complete in
+// order, so each phase sees the previous phase's stores.
 template <int B>
-__device__ void win_task(double* win, int R, int zs, int64_t base, int64_t n, int64_t p, int64_t c) {
+__device__ __forceinline__ void win_task(double* win, double* vbw, int R, int zs, int64_t base, int64_t n, int64_t p, int64_t c) {
   constexpr int RS = WinGeom<B>::RS, LO = WinGeom<B>::LO;
+  // the reflector comes back through LDS (B = 16) or lane reads into scalar
+  // registers (B = 32, where vector registers would not hold it beside the row)
+  constexpr bool kVrLds = B <= 16;
   const int lane = threadIdx.x & 63;
   const int L = (int)((n - c) < B ? (n - c) : B);
   const int nr = (int)(c + L - p - 1);                              // rows p+1 .. c+L-1
@@ -364,62 +370,69 @@ __device__ void win_task(double* win, int R, int zs, int64_t base, int64_t n, in
   const int sp = ring_slot(p, base, R), sc = ring_slot(c, base, R);
   const int dc = (int)(c - p);
 
-  // right reflector on row p, columns c..c+L-1 (element (p, c+l) at rowp[l])
+  // ---- right reflector on row p, columns c..c+L-1 (element (p, c+l) at rowp[l]) ----
   double* rowp = win + sp * RS + (dc + LO);
   double x = lane < L ? rowp[lane] : 0.0;
+  int sr = sp + 1 + lane;
+  sr = sr >= R ? sr - R : sr;
+  double* row = win + sr * RS + (dc - 1 - lane + LO);  // element (p+1+lane, c+l) at row[l]
+  double xr[B];
+  if (lane < nr) {
+#pragma unroll
+    for (int l = 0; l < B; ++l) xr[l] = row[l];
+  }
   double beta, tau, v;
   wave_reflector(x, lane, L, beta, tau, v);
   if (lane < L) rowp[lane] = lane == 0 ? beta : 0.0;
+  if (kVrLds && lane < B) vbw[lane] = v;
+  double vr[B];
+  auto vget = [&](int l) -> double { return vr[l]; };
+  auto vfetch = [&]() {
+#pragma unroll
+    for (int l = 0; l < B; ++l) vr[l] = kVrLds ? vbw[l] : lane_value(v, l);
+  };
   if (tau != 0.0) {
-    double vr[B];
-#pragma unroll
-    for (int l = 0; l < B; ++l) vr[l] = lane_value(v, l);
+    vfetch();
     if (lane < nr) {
-      int sr = sp + 1 + lane;
-      sr = sr >= R ? sr - R : sr;
-      double* row = win + sr * RS + (dc - 1 - lane + LO);  // element (p+1+lane, c+l) at row[l]
-      double xr[B];
-#pragma unroll
-      for (int l = 0; l < B; ++l) xr[l] = row[l];
       double dot = 0.0;
 #pragma unroll
-      for (int l = 0; l < B; ++l) dot += xr[l] * vr[l];
+      for (int l = 0; l < B; ++l) dot += xr[l] * vget(l);
       const double td = tau * dot;
 #pragma unroll
-      for (int l = 0; l < B; ++l) row[l] = xr[l] - td * vr[l];
+      for (int l = 0; l < B; ++l) row[l] = xr[l] - td * vget(l);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
-  // left reflector on column c, rows c..c+L-1 (element (c+l, c) at slot(c+l), offset LO-l)
+  // ---- left reflector on column c, rows c..c+L-1 (element (c+l, c) at slot(c+l), offset LO-l) ----
   int sx = sc + lane;
   sx = sx >= R ? sx - R : sx;
   x = lane < L ? win[sx * RS + LO - lane] : 0.0;
+  int so[B];     // slot of row c+l (the zero slot past row n-1)
+  double xc[B];  // element (c+l, c+1+lane) at offset 1+lane-l+LO of that slot
+#pragma unroll
+  for (int l = 0; l < B; ++l) {
+    int sl = sc + l;
+    sl = sl >= R ? sl - R : sl;
+    so[l] = l < L ? sl : zs;
+  }
+  if (lane < nq) {
+#pragma unroll
+    for (int l = 0; l < B; ++l) xc[l] = win[so[l] * RS + 1 + lane - l + LO];
+  }
   wave_reflector(x, lane, L, beta, tau, v);
   if (lane < L) win[sx * RS + LO - lane] = lane == 0 ? beta : 0.0;
+  if (kVrLds && lane < B) vbw[lane] = v;
   if (tau != 0.0) {
-    double vr[B];
-#pragma unroll
-    for (int l = 0; l < B; ++l) vr[l] = lane_value(v, l);
+    vfetch();
     if (lane < nq) {
-      int so[B];     // slot of row c+l (the zero slot past row n-1)
-      double xc[B];  // element (c+l, c+1+lane) at offset 1+lane-l+LO of that slot
-#pragma unroll
-      for (int l = 0; l < B; ++l) {
-        int sl = sc + l;
-        sl = sl >= R ? sl - R : sl;
-        so[l] = l < L ? sl : zs;
-        xc[l] = win[so[l] * RS + 1 + lane - l + LO];
-      }
       double dot = 0.0;
 #pragma unroll
-      for (int l = 0; l < B; ++l) dot += vr[l] * xc[l];
+      for (int l = 0; l < B; ++l) dot += vget(l) * xc[l];
       const double td = tau * dot;
 #pragma unroll
-      for (int l = 0; l < B; ++l) win[so[l] * RS + 1 + lane - l + LO] = xc[l] - td * vr[l];
+      for (int l = 0; l < B; ++l) win[so[l] * RS + 1 + lane - l + LO] = xc[l] - td * vget(l);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 // First row the (unfinished) sweep s0+i will touch at its task j (j <= 0: it has not started).
@@ -508,7 +521,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
         if (jt >= 0 && jt < ntasks_b<B>(s, n)) {
           const int64_t c = s + 1 + (int64_t)jt * B;
           const int64_t p = jt == 0 ? s : c - B;
-          win_task<B>(win, R, R, 0, n, p, c);
+          win_task<B>(win, win + (R + 1) * RS + wv * B, R, R, 0, n, p, c);
         }
       }
       __syncthreads();
@@ -562,44 +575,48 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Pipelined windowed chase (b = 16): the same window, with the global-memory
-// traffic taken off the step's critical path.
+// Windowed chase with mover waves (b = 16): the window of k_chase_win, with all
+// global-memory traffic taken off the tasks' path.
 // ---------------------------------------------------------------------------
 //
-// Rows for step t+D are requested at step t into a ring of D register sets and
-// written into the window at the end of step t+D-1, so a load has D-1 compute
-// steps to arrive.  Rows leave the window at most b per step, with one store
-// instruction per thread per step (threads with nothing to write store to a
-// private dummy word), so every step issues the same number of loads and stores
-// and the waits the compiler places for the ring stay exact.  The progress of
-// step t-D is published at the end of step t: by then the loads of step t-D+1
-// have completed, and the write-back stores of step t-D were issued before them.
-// A group polls its predecessor once per D steps, for the progress the next D
-// steps of loads need.
+// Waves 0..W-1 only compute (wave i runs task t-3i of sweep s0+i at step t);
+// the kSpecMovers waves after them move rows, during the tasks of the same
+// step.  At step t every mover thread
+//   1. waits for its own loads and stores of step t-1,
+//   2. (one thread) publishes the progress whose rows were stored at step t-2
+//      (all mover threads waited for those stores before the last barrier),
+//   3. writes the rows of step t+1, loaded at step t-1, into the window,
+//   4. stores the rows no sweep of the group touches after step t-1,
+//   5. waits until the predecessor group finished the tasks step t+2 depends
+//      on, and requests the rows of step t+2.
+// One workgroup barrier ends a step.  Rows written in (3) are beyond every row
+// the tasks of step t touch, and rows stored in (4) are below them, so the
+// movers never race the tasks.  The hand-off between consecutive groups costs
+// about four steps.
 
-constexpr int kPipeThreads = 384;  // 6 waves: up to 6 sweeps, the rest move rows
+constexpr int kSpecMovers = 2;
+constexpr int kSpecMaxW = 6;
 
-__host__ __device__ inline int pipe_rows(int b, int W, int D) { return (3 * W + D + 4) * b; }
+__host__ __device__ inline int spec_rows(int b, int W) { return (3 * W + 6) * b; }
 
-size_t chase_pipe_lds_bytes(int b, int W, int D) {
-  return (size_t)(pipe_rows(b, W, D) + 1) * (3 * b + 2) * sizeof(double);  // ring + zero slot
+size_t chase_spec_lds_bytes(int b, int W) {
+  return ((size_t)(spec_rows(b, W) + 1) * (3 * b + 2) + (size_t)16 * b) * sizeof(double);  // ring + zero slot + reflector slots
 }
 
-template <int B, int D>
-__global__ void __launch_bounds__(kPipeThreads) k_chase_pipe(ChaseArgs a) {
-  constexpr int LO = B - 1, RW = 3 * B, RS = RW + 2, NT = kPipeThreads;
-  constexpr int PF = (B * RW + NT - 1) / NT;  // loads (and stores) per thread per step
+template <int B>
+__global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(ChaseArgs a) {
+  constexpr int RW = 3 * B, RS = RW + 2, MT = 64 * kSpecMovers;
+  constexpr int KP = (B * RW / 2 + MT - 1) / MT;  // pairs of doubles per mover thread for B rows
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_flag;
-  __shared__ int64_t s_lo[D + 1];
-  __shared__ int s_done[D + 1];
   const int W = a.W;
-  const int R = pipe_rows(B, W, D);
+  const int R = spec_rows(B, W);
   double* win = lds;
-  for (int e = threadIdx.x; e < RS; e += NT) win[R * RS + e] = 0.0;  // zero slot
   const int wv = threadIdx.x >> 6, tid = threadIdx.x;
-  double* dummy = a.dummy + (size_t)blockIdx.x * NT + tid;
+  const bool mover = wv >= W;
+  const int mt = tid - 64 * W;  // mover thread index (valid when mover)
   const int64_t n = a.n;
+  for (int e = tid; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
 
   for (;;) {
     const int gi = next_group(a);
@@ -615,21 +632,43 @@ __global__ void __launch_bounds__(kPipeThreads) k_chase_pipe(ChaseArgs a) {
     const int prev_total = gi > 0 ? ntasks_b<B>(s0 - 1, n) : 0;
     const int last_total = ntasks_b<B>(sl, n);
     const int first_total = ntasks_b<B>(s0, n);
-    const int64_t base = s0 + 1 - R;  // slot(r) = (r - base) mod R; prefetch blocks never wrap
-    auto slot = [&](int64_t r) -> int { return ring_slot(r, base, R); };
+    auto slot = [&](int64_t r) -> int { return ring_slot(r, s0, R); };
+    // rows the group's first sweep needs up to (and including) step t: [s0, front_end(t))
     auto front_end = [&](int t) -> int64_t {
       const int tt = t < first_total - 1 ? t : first_total - 1;
       const int64_t e = s0 + 1 + (int64_t)(tt + 1) * B;
       return e < n ? e : n;
     };
+    // rows no sweep of the group touches after step t
+    auto final_after = [&](int t) -> int64_t {
+      int64_t lo = n;
+      for (int i = 0; i < nsw; ++i) {
+        const int jn = t + 1 - 3 * i;
+        if (jn < ntasks_b<B>(s0 + i, n)) {
+          const int64_t f = sweep_front(s0 + i, jn, B);
+          lo = f < lo ? f : lo;
+        }
+      }
+      const int64_t cap = front_end(t);
+      return lo < cap ? lo : cap;
+    };
+    // tasks of the last sweep completed after step t
+    auto done_after = [&](int t) -> int {
+      int d = t - 3 * (nsw - 1) + 1;
+      return d < 0 ? 0 : (d > last_total ? last_total : d);
+    };
+    // progress that rows [.., L) written back allow (the next group's step j
+    // needs rows below sl + 2 + (j+1) b and progress j + 3)
+    auto by_rows = [&](int64_t L) -> int { return L - sl - 1 >= 0 ? (int)((L - sl - 1) / B) + 1 : 0; };
+    // each mover wave waits until the previous group's last sweep completed `need` tasks (bounded)
     auto wait_prev = [&](int need) {
-      if (gi == 0 || threadIdx.x != 0) return;
+      if (gi == 0) return;
       need = need < prev_total ? need : prev_total;
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
       while (__hip_atomic_load(&a.progress[gi - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
         if (__builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull ||  // 10 s at 100 MHz
             __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          atomicAdd(a.err, 1);
+          if ((tid & 63) == 0) atomicAdd(a.err, 1);
           s_flag = 1;
           return;
         }
@@ -638,123 +677,131 @@ __global__ void __launch_bounds__(kPipeThreads) k_chase_pipe(ChaseArgs a) {
     };
     if (tid == 0) s_flag = 0;
     __syncthreads();
-    // rows the first D steps need, loaded directly
-    wait_prev(D + 3);
-    __syncthreads();
-    int64_t lo = s0;
-    const int64_t hi0 = s_flag ? s0 : front_end(D - 1);
-    for (int64_t e = tid; e < (hi0 - lo) * RW; e += NT) {
-      const int64_t r = lo + e / RW;
-      const int col = (int)(e % RW);
-      win[slot(r) * RS + col] = bld(a.Bs + r * a.ldb + col);
+    // row movers: a block of rows [r0, r1) is contiguous in the chase storage (row
+    // stride RW = 3B); it is moved as pairs of doubles, pair q = (row r0 + q / (RW/2),
+    // columns 2 (q % (RW/2)) and the next), thread mt taking pairs mt + k MT.  On the
+    // LDS side a pair is one 16-byte access (slot stride and RW are even).
+    auto mv_load = [&](int64_t r0, int64_t r1, double2 (&buf)[KP]) {
+      const int np = (int)(r1 - r0) * (RW / 2);
+      const double* src = a.Bs + r0 * RW + 2 * mt;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const bool ok = mt + k * MT < np;
+        buf[k].x = ok ? bld(src + 2 * k * MT) : 0.0;
+        buf[k].y = ok ? bld(src + 2 * k * MT + 1) : 0.0;
+      }
+    };
+    auto pair_lds = [&](int s_r0, int q) -> double2* {
+      int sl = s_r0 + q / (RW / 2);
+      sl = sl >= R ? sl - R : sl;
+      return reinterpret_cast<double2*>(win + sl * RS + 2 * (q % (RW / 2)));
+    };
+    auto mv_fill = [&](int64_t r0, int64_t r1, const double2 (&buf)[KP]) {
+      const int np = (int)(r1 - r0) * (RW / 2);
+      const int s_r0 = slot(r0);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int q = mt + k * MT;
+        if (q < np) *pair_lds(s_r0, q) = buf[k];
+      }
+    };
+    auto mv_store = [&](int64_t r0, int64_t r1) {
+      // up to B rows per batch (more only when the last sweep starts): LDS reads, then stores
+      for (int64_t rb = r0; rb < r1; rb += B) {
+        const int64_t re = r1 - rb < B ? r1 : rb + B;
+        const int np = (int)(re - rb) * (RW / 2);
+        const int s_r0 = slot(rb);
+        double2 vals[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          const int q = mt + k * MT;
+          vals[k] = q < np ? *pair_lds(s_r0, q) : double2{0.0, 0.0};
+        }
+        double* dst = a.Bs + rb * RW + 2 * mt;
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+          if (mt + k * MT < np) {
+            bst(dst + 2 * k * MT, vals[k].x);
+            bst(dst + 2 * k * MT + 1, vals[k].y);
+          }
+      }
+    };
+    // prologue: rows of steps 0 and 1, loaded directly
+    if (mover) {
+      wait_prev(4);
+      if (!s_flag) {
+        const int64_t hi1 = front_end(1);
+        for (int64_t rb = s0; rb < hi1; rb += B) {
+          double2 buf[KP];
+          const int64_t re = hi1 - rb < B ? hi1 : rb + B;
+          mv_load(rb, re, buf);
+          mv_fill(rb, re, buf);
+        }
+      }
     }
     __syncthreads();
+    int64_t lo = s0;         // rows below lo have been stored
+    int64_t lo_hist[3] = {s0, s0, s0};  // lo after the stores of steps t-1, t-2, t-3
     int published = 0;
-    double regs[D][PF];
-    for (int t0 = 0; t0 < tend && !s_flag; t0 += D) {
-      wait_prev(t0 + 2 * D + 3);
-      __syncthreads();
-      if (s_flag) break;
-#pragma unroll
-      for (int S = 0; S < D; ++S) {
-        const int t = t0 + S;
-        if (t >= tend) break;
-        CHASE_MARK(gi, t, 0);
-        // (1) request the rows of step t+D
-        {
-          const int64_t r0 = front_end(t + D - 1);
-          const int npf = (int)((front_end(t + D) - r0) * RW);
-#pragma unroll
-          for (int k = 0; k < PF; ++k) {
-            const int e = tid + k * NT;
-            const int64_t idx = e < npf ? r0 * a.ldb + e : 0;
-            regs[S][k] = bld(a.Bs + idx);
-          }
-        }
-        CHASE_MARK(gi, t, 1);
-        // (2) compute: wave i runs task t-3i of sweep s0+i
+    double2 regs[KP];
+    for (int t = 0; t < tend && !s_flag; ++t) {
+      CHASE_MARK(gi, t, 0);
+      if (!mover) {
         if (wv < nsw) {
           const int64_t s = s0 + wv;
           const int jt = t - 3 * wv;
           if (jt >= 0 && jt < ntasks_b<B>(s, n)) {
             const int64_t c = s + 1 + (int64_t)jt * B;
             const int64_t p = jt == 0 ? s : c - B;
-            win_task<B>(win, R, R, base, n, p, c);
+            win_task<B>(win, win + (R + 1) * RS + wv * B, R, R, s0, n, p, c);
           }
         }
-        CHASE_MARK(gi, t, 2);
-        __syncthreads();
-        CHASE_MARK(gi, t, 3);
-        // (3) write back at most B rows no unfinished sweep touches again
-        {
-          int64_t nlo = n;
-          for (int i = 0; i < nsw; ++i) {
-            const int jn = t + 1 - 3 * i;
-            if (jn < ntasks_b<B>(s0 + i, n)) {
-              const int64_t f = sweep_front(s0 + i, jn, B);
-              nlo = f < nlo ? f : nlo;
-            }
-          }
-          const int64_t cap = front_end(t);
-          nlo = nlo < cap ? nlo : cap;
-          nlo = nlo < lo + B ? nlo : lo + B;
-          const int nwb = (int)((nlo - lo) * RW);
-#pragma unroll
-          for (int k = 0; k < PF; ++k) {
-            const int e = tid + k * NT;
-            const bool ok = e < nwb;
-            const int64_t r = lo + (ok ? e / RW : 0);
-            const int col = ok ? e % RW : 0;
-            const double v = win[(ok ? slot(r) : 0) * RS + col];
-            bst(ok ? a.Bs + r * a.ldb + col : dummy, v);
-          }
-          lo = nlo;
-        }
-        CHASE_MARK(gi, t, 4);
-        // (4) rows of step t+1 (requested at step t-D+1) into the window
-        if (t - D + 1 >= 0) {
-          const int64_t r0 = front_end(t);
-          const int nst = (int)((front_end(t + 1) - r0) * RW);
-#pragma unroll
-          for (int k = 0; k < PF; ++k) {
-            const int e = tid + k * NT;
-            if (e < nst) win[slot(r0 + e / RW) * RS + e % RW] = regs[(S + 1) % D][k];
-          }
-        }
-        if (tid == 0) {
-          int dl = t - 3 * (nsw - 1) + 1;
-          dl = dl < 0 ? 0 : (dl > last_total ? last_total : dl);
-          s_lo[t % (D + 1)] = lo;
-          s_done[t % (D + 1)] = dl;
-        }
-        CHASE_MARK(gi, t, 5);
-        __syncthreads();
-        CHASE_MARK(gi, t, 6);
-        // (5) publish the progress of step t-D
-        if (tid == 0 && t - D >= 0) {
-          const int64_t L = s_lo[(t - D) % (D + 1)];
-          int P = s_done[(t - D) % (D + 1)];
-          const int64_t byrows = L - sl - 1 >= 0 ? (L - sl - 1) / B + 1 : 0;
-          P = byrows < P ? (int)byrows : P;
+        CHASE_MARK(gi, t, 1);
+      } else {
+        // 1. own loads and stores of step t-1 complete
+        __builtin_amdgcn_s_waitcnt(0);
+        CHASE_MARK_IF(mt == 0, gi, t, 3);
+        // 2. publish: rows stored at step t-2 are complete in every mover thread
+        if (mt == 0 && t >= 2) {
+          int P = done_after(t - 3 >= 0 ? t - 3 : -1);
+          const int br = by_rows(lo_hist[1]);
+          P = br < P ? br : P;
           P = P < last_total - 1 ? P : last_total - 1;
           if (P > published) {
             published = P;
             __hip_atomic_store(&a.progress[gi], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        CHASE_MARK(gi, t, 7);
+        // 3. rows of step t+1 (requested at step t-1) into the window
+        if (t >= 1) mv_fill(front_end(t), front_end(t + 1), regs);
+        // 4. store the rows final after step t-1
+        if (t >= 1) {
+          const int64_t nlo = final_after(t - 1);
+          mv_store(lo, nlo);
+          lo = nlo > lo ? nlo : lo;
+        }
+        lo_hist[2] = lo_hist[1];
+        lo_hist[1] = lo_hist[0];
+        lo_hist[0] = lo;
+        CHASE_MARK_IF(mt == 0, gi, t, 4);
+        // 5. rows of step t+2
+        wait_prev(t + 5);
+        CHASE_MARK_IF(mt == 0, gi, t, 5);
+        if (!s_flag) mv_load(front_end(t + 1), front_end(t + 2), regs);
+        CHASE_MARK_IF(mt == 0, gi, t, 6);
       }
+      __syncthreads();
+      CHASE_MARK(gi, t, 2);
     }
-    // flush the window and mark the group complete
-    const int64_t hi_end = front_end(tend);
-    for (int64_t e = tid; e < (hi_end - lo) * RW; e += NT) {
-      const int64_t r = lo + e / RW;
-      const int col = (int)(e % RW);
-      bst(a.Bs + r * a.ldb + col, win[slot(r) * RS + col]);
+    // epilogue: store the rest of the window, then mark the group complete
+    if (mover) {
+      __builtin_amdgcn_s_waitcnt(0);
+      mv_store(lo, front_end(tend));
+      __builtin_amdgcn_s_waitcnt(0);
     }
-    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (mover && mt == 0 && !s_flag)
+      __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
 }
@@ -767,24 +814,24 @@ __global__ void k_chase_extract(const double* __restrict__ Bs, int64_t ldb, int6
   }
 }
 
-static bool use_pipe(int b, int W) { return b == 16 && W <= kPipeThreads / 64 && chase_pipe_lds_bytes(b, W, 3) <= 159 * 1024; }
+static bool use_spec(int b, int W) { return b == 16 && W <= kSpecMaxW && chase_spec_lds_bytes(b, W) <= 159 * 1024; }
 static bool use_window(int b, int W) {
-  return !use_pipe(b, W) && (b == 16 || b == 32) && chase_win_lds_bytes(b, W) <= 159 * 1024;
+  return !use_spec(b, W) && (b == 16 || b == 32) && chase_win_lds_bytes(b, W) <= 159 * 1024;
 }
 
 static const void* chase_fn(int b, int W) {
-  if (use_pipe(b, W)) return (const void*)k_chase_pipe<16, 3>;
+  if (use_spec(b, W)) return (const void*)k_chase_spec<16>;
   if (use_window(b, W)) return b == 16 ? (const void*)k_chase_win<16> : (const void*)k_chase_win<32>;
   return (const void*)k_chase;
 }
 
 static int chase_threads(int b, int W) {
-  if (use_pipe(b, W)) return kPipeThreads;
+  if (use_spec(b, W)) return 64 * (W + kSpecMovers);
   return use_window(b, W) ? 64 * (W > WinGeom<16>::MIN_WAVES ? W : WinGeom<16>::MIN_WAVES) : 64 * W;
 }
 
 static size_t chase_launch_lds(int b, int W) {
-  if (use_pipe(b, W)) return chase_pipe_lds_bytes(b, W, 3);
+  if (use_spec(b, W)) return chase_spec_lds_bytes(b, W);
   return use_window(b, W) ? chase_win_lds_bytes(b, W) : chase_lds_bytes(b, W);
 }
 
@@ -812,7 +859,7 @@ hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st) {
   if (a.n > 1) {
     hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, st, a.progress, 0, (int64_t)a.ngroups + 1);
     const dim3 block(chase_threads(a.b, a.W));
-    if (fn == (const void*)k_chase_pipe<16, 3>) hipLaunchKernelGGL((k_chase_pipe<16, 3>), dim3(grid), block, lds, st, a);
+    if (fn == (const void*)k_chase_spec<16>) hipLaunchKernelGGL(k_chase_spec<16>, dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_win<16>) hipLaunchKernelGGL(k_chase_win<16>, dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_win<32>) hipLaunchKernelGGL(k_chase_win<32>, dim3(grid), block, lds, st, a);
     else hipLaunchKernelGGL(k_chase, dim3(grid), block, lds, st, a);

@@ -21,14 +21,51 @@ namespace {
 thread_local std::string g_last_error;
 
 // Optional per-stage event timing (see svdv_timing in the header).
+// Per kernel class (0: trailing update, 1: panel), every launch of the last
+// timed call is bracketed by an event pair and its algorithmic flops and bytes
+// are recorded on the host.
+struct KernelLog {
+  std::vector<hipEvent_t> ev;  // pool, pairs (2i, 2i+1)
+  std::vector<double> flops, bytes;
+  size_t used = 0;
+  void reset() {
+    used = 0;
+    flops.clear();
+    bytes.clear();
+  }
+  hipEvent_t next() {
+    if (used == ev.size()) {
+      hipEvent_t e = nullptr;
+      hipEventCreate(&e);
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+};
 struct Timing {
   bool enabled = false;
+  bool kernels = false;  // also bracket every stage-1 launch (svdv_timing(2))
   bool valid = false;
   hipEvent_t ev[7] = {};
+  KernelLog klog[2];
   void mark(int i, hipStream_t st) {
     if (!enabled) return;
     if (!ev[i]) hipEventCreate(&ev[i]);
     hipEventRecord(ev[i], st);
+  }
+  void begin_call() {
+    valid = false;
+    klog[0].reset();
+    klog[1].reset();
+  }
+  void kbegin(int kind, hipStream_t st) {
+    if (kernels) hipEventRecord(klog[kind].next(), st);
+  }
+  void kend(int kind, hipStream_t st, double fl, double by) {
+    if (!kernels) return;
+    hipEventRecord(klog[kind].next(), st);
+    klog[kind].flops.push_back(fl);
+    klog[kind].bytes.push_back(by);
   }
 };
 thread_local Timing g_timing;
@@ -221,7 +258,7 @@ size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 // Persistent grid of the bulge chase: every workgroup must be resident at once.
 // SVDV_CHASE_GRID (debugging aid) caps it further, e.g. 1 = all groups in one workgroup.
 int chase_grid(int ngroups, int b, int W) {
-  int g = std::min<int>({ngroups, chase_max_groups_resident(b, W), (int)(kChaseDummy / 384)});
+  int g = std::min<int>(ngroups, chase_max_groups_resident(b, W));
   if (const char* env = getenv("SVDV_CHASE_GRID")) {
     const int cap = atoi(env);
     if (cap > 0) g = std::min(g, cap);
@@ -230,7 +267,7 @@ int chase_grid(int ngroups, int b, int W) {
 }
 
 struct Layout {
-  size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, dummy, total;
+  size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, total;
 };
 
 Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_width, int64_t ldw) {
@@ -255,7 +292,6 @@ Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_w
   L.d = take((size_t)N * 8);
   L.e = take((size_t)N * 8);
   L.work = take((size_t)(2 * N + 2) * 8);
-  L.dummy = take((size_t)kChaseDummy * 8);
   L.total = off;
   return L;
 }
@@ -281,7 +317,10 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
     a.V = vws + lv.voff;
     a.ldv = lv.ldv;
     a.Tm = tws + lv.toff;
+    g_timing.kbegin(1, st);
     HIPCHK(launch_chunk_qr<T>(cfg.tile, a, st));
+    // Householder QR of P chunks of (chunk rows x bw): 2 r bw^2 flops, panel read and written once
+    g_timing.kend(1, st, 2.0 * (double)lv.h * bw * bw, 2.0 * sizeof(T) * (double)lv.h * bw);
   }
   if (pc + bw < ncols) {
     for (auto& lv : levels) {
@@ -299,7 +338,11 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
       a.ldt = cfg.tile;
       a.k = (int32_t)(lv.P == 1 ? std::min<int64_t>(bw, lv.h) : bw);
       a.vec = larfb_vec_ok(a);
+      g_timing.kbegin(0, st);
       HIPCHK(launch_larfb<T>(cfg.tile, cfg.threads / 64, cfg.inner_block, a, st));
+      // C (rows x w) read and written once, V (rows x k) read once; 4 rows w k flops
+      const double w = (double)(a.col1 - a.col0);
+      g_timing.kend(0, st, 4.0 * (double)lv.h * w * a.k, sizeof(T) * ((double)lv.h * w * 2.0 + (double)lv.h * a.k));
     }
   }
   return SVDV_OK;
@@ -362,7 +405,7 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   double* e = e_out ? e_out : (double*)(ws + L.e);
   double* work = (double*)(ws + L.work);
 
-  g_timing.valid = false;
+  g_timing.begin_call();
   g_timing.mark(0, st);
   HIPCHK(launch_stage_in<T>(A, m, n, lda, transpose, W, ldw, amax, expo, st));
   g_timing.mark(1, st);
@@ -386,7 +429,6 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   ca.err = err;
   ca.d = d;
   ca.e = e;
-  ca.dummy = (double*)(ws + L.dummy);
   int grid = chase_grid(ca.ngroups, cfg.tile, cfg.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
@@ -498,7 +540,6 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   ca.err = (int*)(ws + L.err);
   ca.d = d;
   ca.e = e ? e : (double*)(ws + L.e);
-  ca.dummy = (double*)(ws + L.dummy);
   if (const char* env = getenv("SVDV_CHASE_GROUPS")) {  // debugging aid: run only the first groups
     const int cap = atoi(env);
     if (cap > 0 && cap < ca.ngroups) ca.ngroups = cap;
@@ -591,6 +632,7 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
 
 int svdv_timing(int enable) {
   g_timing.enabled = enable != 0;
+  g_timing.kernels = enable >= 2;
   g_timing.valid = false;
   return SVDV_OK;
 }
@@ -611,6 +653,28 @@ int svdv_last_timing(double* ms, int n) {
     ms[k++] = t;
   }
   return k;
+}
+
+int svdv_last_kernel_stats(int kind, double* out, int n) {
+  if (!out || n < 4) return fail(SVDV_ERR_INVALID_ARG, "out needs 4 entries");
+  if (kind != 0 && kind != 1) return fail(SVDV_ERR_INVALID_ARG, "kind must be 0 (trailing update) or 1 (panel)");
+  if (!g_timing.valid) return fail(SVDV_ERR_INVALID_ARG, "no timed call recorded (enable svdv_timing first)");
+  const KernelLog& L = g_timing.klog[kind];
+  const size_t launches = L.flops.size();
+  double ms = 0.0, fl = 0.0, by = 0.0;
+  if (launches) HIPCHK(hipEventSynchronize(L.ev[2 * launches - 1]));
+  for (size_t i = 0; i < launches; ++i) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, L.ev[2 * i], L.ev[2 * i + 1]));
+    ms += t;
+    fl += L.flops[i];
+    by += L.bytes[i];
+  }
+  out[0] = (double)launches;
+  out[1] = ms;
+  out[2] = fl;
+  out[3] = by;
+  return 4;
 }
 
 int svdv_release(void) {
@@ -654,7 +718,6 @@ extern "C" int svdv_debug_chase(const double* band, int64_t n, int64_t b, int64_
   ca.err = (int*)(ws + L.err);
   ca.d = (double*)(ws + L.d);
   ca.e = (double*)(ws + L.e);
-  ca.dummy = (double*)(ws + L.dummy);
   int grid = chase_grid(ca.ngroups, (int)b, W);
   if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);

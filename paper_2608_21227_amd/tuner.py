@@ -191,9 +191,11 @@ def main(argv=None) -> None:
     ap.add_argument("--table", default=TABLE_PATH)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--time-budget", type=float, default=0.0, help="stop measuring after this many seconds")
+    ap.add_argument("--slow-ms", type=float, default=500.0)
     args = ap.parse_args(argv)
     n, dtype = args.n, args.dtype
-    db = args.db or os.path.join(_HERE, f"tuning_{n}_{dtype}.jsonl")
+    db = args.db or os.path.join(_HERE, "tuning", f"tuning_{n}_{dtype}.jsonl")
+    os.makedirs(os.path.dirname(db) or ".", exist_ok=True)
     rng = np.random.default_rng(np.random.SeedSequence(260821227, spawn_key=(1, n, 0 if dtype == "float32" else 1)))
     a_np = rng.standard_normal((n, n)).astype(dtype)
     a = torch.from_numpy(np.ascontiguousarray(a_np.T)).t().cuda()
@@ -205,7 +207,12 @@ def main(argv=None) -> None:
     def measure(cfg):
         if args.time_budget and time.time() - t0 > args.time_budget:
             raise TimeoutError
-        return measure_fn(a, cfg, args.reps)
+        # configurations slower than `slow_ms` per call get one timed call after the
+        # warm-up (their rank is not in doubt and they would dominate the run time)
+        first = measure_fn(a, cfg, 1, warmup=1)
+        if first[0] > args.slow_ms:
+            return first
+        return measure_fn(a, cfg, args.reps, warmup=0)
 
     try:
         recs = tune(n, dtype, cfgs, db, measure, progress=lambda m: print("[tune]", m, flush=True))
