@@ -56,15 +56,17 @@ typedef enum {
  *                number of panel steps (2 * ceil(n / TS)): the paper's only
  *                pipeline parameter.
  *   threads      workgroup size of the stage-1 trailing-update kernel,
- *                {64, 128, 256, 512, 1024}; each wave owns its own column tiles.
- *   inner_block  16-column MFMA tiles held per wave in the trailing update,
- *                {1, 2, 4, 8} (register blocking).
+ *                {64, 128, 256, 512, 1024}; its waves split the rows of one
+ *                panel chunk (the split-K of Algorithm 2).
+ *   inner_block  16-column MFMA tiles per workgroup of the trailing update,
+ *                {1, 2, 4, 8} (columns per block, register blocking).
  *   sweep_width  bulge-chasing sweeps advanced together by one workgroup in
  *                stage 2, {1, ..., 8}.
  *   update_precision  0 = trailing updates in the input precision;
  *                2 = BF16 MFMA operands, 3 = FP16 MFMA operands (float32 input
- *                only; accumulation stays float32, panels, stage 2 and stage 3
- *                are unaffected).
+ *                only, and configurations whose trailing-update strip fits in
+ *                registers; accumulation stays float32, panels with their
+ *                float64 norms, stage 2 and stage 3 are unaffected).
  */
 typedef struct {
   int32_t tile;

@@ -52,6 +52,34 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = dpp_i<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+// Sums over the first 16 or 32 lanes only (the other lanes must hold 0): the
+// same DPP tree as wave_sum stopped after the stages that reach lane 15 (one
+// row) or lane 31 (two rows), so the value equals wave_sum's bitwise.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x114>(v);
+  v += dpp_d<0x118>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 15);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 15);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_sum32(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x114>(v);
+  v += dpp_d<0x118>(v);
+  v += dpp_d<0x142>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 31);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 31);
+  return __hiloint2double(hi, lo);
+}
+
+// LDS pointer types: indexing through them keeps address arithmetic in 32 bits.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f<0xb1>(v);   // quad_perm 1,0,3,2
   v += dpp_f<0x4e>(v);   // quad_perm 2,3,0,1
@@ -81,6 +109,30 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 }
 __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Reduced-precision MFMA 16x16x16 with float32 accumulation: lane l supplies
+// A[l % 16][4 (l / 16) + i] and B[4 (l / 16) + i][l % 16], i = 0..3, rounded to
+// BF16 (PREC 2, round to nearest even) or FP16 (PREC 3); the result layout is
+// that of the float32 16x16x4 instruction.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short f32_to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma16x16(const float (&a)[4], const float (&b)[4], f32x4 c) {
+  if constexpr (PREC == 2) {
+    const bf16x4 av = {f32_to_bf16(a[0]), f32_to_bf16(a[1]), f32_to_bf16(a[2]), f32_to_bf16(a[3])};
+    const bf16x4 bv = {f32_to_bf16(b[0]), f32_to_bf16(b[1]), f32_to_bf16(b[2]), f32_to_bf16(b[3])};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  } else {
+    const f16x4 av = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+    const f16x4 bv = {(_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+  }
 }
 
 // Row of the 16x16 MFMA result held in register i of lane-group g (g = lane / 16):

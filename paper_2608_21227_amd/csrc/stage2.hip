@@ -330,8 +330,10 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // Householder reflector H = I - tau v v^T with H x = beta e_1, for the vector x
 // held one entry per lane (lanes >= L hold 0).  v is returned per lane (v_0 = 1,
 // zero beyond L); x = 0 below its first entry gives tau = 0 (H = I).
+template <int B>
 __device__ __forceinline__ void wave_reflector(double x, int lane, int L, double& beta, double& tau, double& v) {
-  const double ss = wave_sum((lane >= 1 && lane < L) ? x * x : 0.0);
+  const double sq = (lane >= 1 && lane < L) ? x * x : 0.0;  // L <= B: only the first B lanes contribute
+  const double ss = B <= 16 ? row_sum16(sq) : row_sum32(sq);
   const double alpha = lane_value(x, 0);
   double scal = 0.0;
   beta = alpha;
@@ -358,7 +360,8 @@ __device__ __forceinline__ void wave_reflector(double x, int lane, int L, double
 // right update over distinct banks.  LDS operations of one wave complete in
 // order, so each phase sees the previous phase's stores.
 template <int B>
-__device__ __forceinline__ void win_task(double* win, double* vbw, int R, int zs, int64_t base, int64_t n, int64_t p, int64_t c) {
+__device__ __forceinline__ void win_task(lds_f64* win, lds_f64* vbw, int R, int zs, int64_t base, int64_t n, int64_t p,
+                                         int64_t c) {
   constexpr int RS = WinGeom<B>::RS, LO = WinGeom<B>::LO;
   // the reflector comes back through LDS (B = 16) or lane reads into scalar
   // registers (B = 32, where vector registers would not hold it beside the row)
@@ -371,18 +374,19 @@ __device__ __forceinline__ void win_task(double* win, double* vbw, int R, int zs
   const int dc = (int)(c - p);
 
   // ---- right reflector on row p, columns c..c+L-1 (element (p, c+l) at rowp[l]) ----
-  double* rowp = win + sp * RS + (dc + LO);
+  lds_f64* rowp = win + sp * RS + (dc + LO);
   double x = lane < L ? rowp[lane] : 0.0;
-  int sr = sp + 1 + lane;
+  // lanes past the last row read (and later leave alone) row p+1, so the loads
+  // need no branch and overlap the reduction below
+  const int lr = lane < nr ? lane : 0;
+  int sr = sp + 1 + lr;
   sr = sr >= R ? sr - R : sr;
-  double* row = win + sr * RS + (dc - 1 - lane + LO);  // element (p+1+lane, c+l) at row[l]
+  lds_f64* row = win + sr * RS + (dc - 1 - lr + LO);  // element (p+1+lr, c+l) at row[l]
   double xr[B];
-  if (lane < nr) {
 #pragma unroll
-    for (int l = 0; l < B; ++l) xr[l] = row[l];
-  }
+  for (int l = 0; l < B; ++l) xr[l] = row[l];
   double beta, tau, v;
-  wave_reflector(x, lane, L, beta, tau, v);
+  wave_reflector<B>(x, lane, L, beta, tau, v);
   if (lane < L) rowp[lane] = lane == 0 ? beta : 0.0;
   if (kVrLds && lane < B) vbw[lane] = v;
   double vr[B];
@@ -415,11 +419,10 @@ __device__ __forceinline__ void win_task(double* win, double* vbw, int R, int zs
     sl = sl >= R ? sl - R : sl;
     so[l] = l < L ? sl : zs;
   }
-  if (lane < nq) {
+  const int lq = lane < nq ? lane : 0;  // as above: lanes past the last column read column c+1
 #pragma unroll
-    for (int l = 0; l < B; ++l) xc[l] = win[so[l] * RS + 1 + lane - l + LO];
-  }
-  wave_reflector(x, lane, L, beta, tau, v);
+  for (int l = 0; l < B; ++l) xc[l] = win[so[l] * RS + 1 + lq - l + LO];
+  wave_reflector<B>(x, lane, L, beta, tau, v);
   if (lane < L) win[sx * RS + LO - lane] = lane == 0 ? beta : 0.0;
   if (kVrLds && lane < B) vbw[lane] = v;
   if (tau != 0.0) {
@@ -446,7 +449,7 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
   extern __shared__ __align__(16) double lds[];
   const int W = a.W;
   const int R = win_rows(B, W);
-  double* win = lds;
+  lds_f64* win = (lds_f64*)lds;
   for (int e = threadIdx.x; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
   const int wv = threadIdx.x >> 6;
   const int nthr = blockDim.x;
@@ -611,7 +614,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
   __shared__ int s_flag;
   const int W = a.W;
   const int R = spec_rows(B, W);
-  double* win = lds;
+  lds_f64* win = (lds_f64*)lds;
   const int wv = threadIdx.x >> 6, tid = threadIdx.x;
   const bool mover = wv >= W;
   const int mt = tid - 64 * W;  // mover thread index (valid when mover)
@@ -681,7 +684,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
     // stride RW = 3B); it is moved as pairs of doubles, pair q = (row r0 + q / (RW/2),
     // columns 2 (q % (RW/2)) and the next), thread mt taking pairs mt + k MT.  On the
     // LDS side a pair is one 16-byte access (slot stride and RW are even).
-    auto mv_load = [&](int64_t r0, int64_t r1, double2 (&buf)[KP]) {
+    auto mv_load = [&](int64_t r0, int64_t r1, f64x2 (&buf)[KP]) {
       const int np = (int)(r1 - r0) * (RW / 2);
       const double* src = a.Bs + r0 * RW + 2 * mt;
 #pragma unroll
@@ -691,12 +694,12 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
         buf[k].y = ok ? bld(src + 2 * k * MT + 1) : 0.0;
       }
     };
-    auto pair_lds = [&](int s_r0, int q) -> double2* {
+    auto pair_lds = [&](int s_r0, int q) -> lds_f64x2* {
       int sl = s_r0 + q / (RW / 2);
       sl = sl >= R ? sl - R : sl;
-      return reinterpret_cast<double2*>(win + sl * RS + 2 * (q % (RW / 2)));
+      return (lds_f64x2*)(win + sl * RS + 2 * (q % (RW / 2)));
     };
-    auto mv_fill = [&](int64_t r0, int64_t r1, const double2 (&buf)[KP]) {
+    auto mv_fill = [&](int64_t r0, int64_t r1, const f64x2 (&buf)[KP]) {
       const int np = (int)(r1 - r0) * (RW / 2);
       const int s_r0 = slot(r0);
 #pragma unroll
@@ -711,11 +714,11 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
         const int64_t re = r1 - rb < B ? r1 : rb + B;
         const int np = (int)(re - rb) * (RW / 2);
         const int s_r0 = slot(rb);
-        double2 vals[KP];
+        f64x2 vals[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
           const int q = mt + k * MT;
-          vals[k] = q < np ? *pair_lds(s_r0, q) : double2{0.0, 0.0};
+          vals[k] = q < np ? *pair_lds(s_r0, q) : f64x2{0.0, 0.0};
         }
         double* dst = a.Bs + rb * RW + 2 * mt;
 #pragma unroll
@@ -732,7 +735,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
       if (!s_flag) {
         const int64_t hi1 = front_end(1);
         for (int64_t rb = s0; rb < hi1; rb += B) {
-          double2 buf[KP];
+          f64x2 buf[KP];
           const int64_t re = hi1 - rb < B ? hi1 : rb + B;
           mv_load(rb, re, buf);
           mv_fill(rb, re, buf);
@@ -743,7 +746,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
     int64_t lo = s0;         // rows below lo have been stored
     int64_t lo_hist[3] = {s0, s0, s0};  // lo after the stores of steps t-1, t-2, t-3
     int published = 0;
-    double2 regs[KP];
+    f64x2 regs[KP];
     for (int t = 0; t < tend && !s_flag; ++t) {
       CHASE_MARK(gi, t, 0);
       if (!mover) {

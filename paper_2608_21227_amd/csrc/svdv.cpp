@@ -106,7 +106,12 @@ int check_config_impl(int64_t m, int64_t n, int dtype, const svdv_config& c) {
   if (!(c.inner_block == 1 || c.inner_block == 2 || c.inner_block == 4 || c.inner_block == 8))
     return fail(SVDV_ERR_UNSUPPORTED, "inner_block must be 1, 2, 4 or 8");
   if (c.sweep_width < 1 || c.sweep_width > 8) return fail(SVDV_ERR_UNSUPPORTED, "sweep_width must be in 1..8");
-  if (c.update_precision != 0) return fail(SVDV_ERR_UNSUPPORTED, "update_precision other than 0 is not built");
+  if (c.update_precision != 0 && c.update_precision != 2 && c.update_precision != 3)
+    return fail(SVDV_ERR_UNSUPPORTED, "update_precision must be 0 (input precision), 2 (BF16) or 3 (FP16)");
+  if (c.update_precision != 0 &&
+      (dtype != SVDV_F32 || !larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)))
+    return fail(SVDV_ERR_UNSUPPORTED, "BF16/FP16 trailing updates need float32 input and a configuration whose "
+                                      "strip fits in registers");
   if (dtype == SVDV_F64 && c.tile > 64) return fail(SVDV_ERR_UNSUPPORTED, "float64 supports tiles up to 64");
   const bool ok = dtype == SVDV_F32 ? larfb_ok<float>(c.tile, c.threads, c.inner_block)
                                     : larfb_ok<double>(c.tile, c.threads, c.inner_block);
@@ -338,6 +343,7 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
       a.ldt = cfg.tile;
       a.k = (int32_t)(lv.P == 1 ? std::min<int64_t>(bw, lv.h) : bw);
       a.vec = larfb_vec_ok(a);
+      a.prec = cfg.update_precision;
       g_timing.kbegin(0, st);
       HIPCHK(launch_larfb<T>(cfg.tile, cfg.threads / 64, cfg.inner_block, a, st));
       // C (rows x w) read and written once, V (rows x k) read once; 4 rows w k flops
@@ -586,6 +592,8 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
   if (k > c.tile) return fail(SVDV_ERR_UNSUPPORTED, "k exceeds cfg->tile");
   const bool tall_ok = dtype == SVDV_F32 ? larfb_stream_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
                                           : larfb_stream_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
+  if (vrows > 32768 / c.tile && c.update_precision != 0)
+    return fail(SVDV_ERR_UNSUPPORTED, "BF16/FP16 updates need a reflector length of at most 32768 / cfg->tile");
   if (vrows > 32768 / c.tile && !tall_ok)
     return fail(SVDV_ERR_UNSUPPORTED, "reflector length exceeds 32768 / cfg->tile, which this configuration "
                                       "(threads, inner_block) only handles in registers");
@@ -606,6 +614,7 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
     a.ldt = ldt;
     a.k = (int32_t)k;
     a.vec = larfb_vec_ok(a);
+    a.prec = c.update_precision;
     HIPCHK(launch_larfb<T>(c.tile, c.threads / 64, c.inner_block, a, st));
     return SVDV_OK;
   };

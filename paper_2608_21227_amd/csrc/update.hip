@@ -94,7 +94,8 @@ __device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int H
   }
 }
 
-template <typename T, int KT, int IB, int NW, int SPW, bool VEC>
+// PREC 0: MFMA in T; PREC 2 / 3 (T = float): BF16 / FP16 operands, float32 accumulation.
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
 __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
@@ -142,24 +143,35 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+  if constexpr (PREC == 0) {
 #pragma unroll
-  for (int j = 0; j < SPW; ++j)
+    for (int j = 0; j < SPW; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[j][mt][i], cr[j][nt][i], Z[mt][nt]);
+  } else {
+    // one 16x16x16 instruction per slab: K = the 16 rows, lane (g, nl) holding rows 4g..4g+3
+#pragma unroll
+    for (int j = 0; j < SPW; ++j)
 #pragma unroll
       for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[j][mt][i], cr[j][nt][i], Z[mt][nt]);
+        for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16x16<PREC>(vr[j][mt], cr[j][nt], Z[mt][nt]);
+  }
 
   // pass-2 operands (reflectors along K, rows along lanes), requested before the reduction
-  // A[m = row][k = reflector]: lane (g, nl) holds -V[q0 + nl][4 kk + g], kk = 0..KR/4-1
+  // A[m = row][k = reflector]: lane (g, nl) holds -V[q0 + nl][r], r = 4 kk + g (K = 4 per
+  // instruction) or, for the 16x16x16 forms, r = 16 (kk / 4) + 4 g + kk % 4
   T va[SPW][KR / 4];
 #pragma unroll
   for (int j = 0; j < SPW; ++j) {
     const int q = (wv + j * NW) * 16 + nl;
 #pragma unroll
     for (int kk = 0; kk < KR / 4; ++kk) {
-      const int r = 4 * kk + g;
+      const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
       va[j][kk] = (q < Hc && r < k) ? -V[q + (int64_t)r * a.ldv] : T(0);
     }
   }
@@ -195,9 +207,11 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   // B[k = reflector][n = column]: lane (g, nl) holds Z'[4 kk + g][16 nt + nl]
   T zb[KR / 4][IB];
 #pragma unroll
-  for (int kk = 0; kk < KR / 4; ++kk)
+  for (int kk = 0; kk < KR / 4; ++kk) {
+    const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
 #pragma unroll
-    for (int nt = 0; nt < IB; ++nt) zb[kk][nt] = Zp[(4 * kk + g) * CB + nt * 16 + nl];
+    for (int nt = 0; nt < IB; ++nt) zb[kk][nt] = Zp[r * CB + nt * 16 + nl];
+  }
 #pragma unroll
   for (int j = 0; j < SPW; ++j) {
     const int s = wv + j * NW;
@@ -205,10 +219,21 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
     AccT acc[IB];
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) acc[nt] = AccT{cr[j][nt][0], cr[j][nt][1], cr[j][nt][2], cr[j][nt][3]};
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int kk = 0; kk < KR / 4; ++kk)
+      for (int kk = 0; kk < KR / 4; ++kk)
 #pragma unroll
-      for (int nt = 0; nt < IB; ++nt) acc[nt] = mfma16(va[j][kk], zb[kk][nt], acc[nt]);
+        for (int nt = 0; nt < IB; ++nt) acc[nt] = mfma16(va[j][kk], zb[kk][nt], acc[nt]);
+    } else {
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < IB; ++nt) {
+          const float av[4] = {va[j][4 * kt], va[j][4 * kt + 1], va[j][4 * kt + 2], va[j][4 * kt + 3]};
+          const float bv[4] = {zb[4 * kt][nt], zb[4 * kt + 1][nt], zb[4 * kt + 2][nt], zb[4 * kt + 3][nt]};
+          acc[nt] = mfma16x16<PREC>(av, bv, acc[nt]);
+        }
+    }
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) store_c<T, VEC>(a, c, Hc, s * 16, g, colbase + nt * 16 + nl, acc[nt]);
   }
@@ -380,20 +405,20 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_stream(LarfbArgs<T> a) {
   }
 }
 
-template <typename T, int KT, int IB, int NW, bool VEC>
+template <typename T, int KT, int IB, int NW, bool VEC, int PREC>
 static hipError_t launch_larfb_reg(const LarfbArgs<T>& a, hipStream_t st) {
   constexpr int SPW = larfb_spw(KT * 16, NW);
   constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
   static bool configured = false;
   if (!configured) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg<T, KT, IB, NW, SPW, VEC>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg<T, KT, IB, NW, SPW, VEC, PREC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     configured = true;
   }
   const int64_t ncols = a.col1 - a.col0;
   const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), (unsigned)a.P);
-  hipLaunchKernelGGL((k_larfb_reg<T, KT, IB, NW, SPW, VEC>), grid, dim3(NW * 64), lds, st, a);
+  hipLaunchKernelGGL((k_larfb_reg<T, KT, IB, NW, SPW, VEC, PREC>), grid, dim3(NW * 64), lds, st, a);
   return hipGetLastError();
 }
 
@@ -421,11 +446,17 @@ static hipError_t launch_larfb_nw(const LarfbArgs<T>& a, hipStream_t st) {
   if constexpr (larfb_reg_valid<T>(KT, IB, NW)) {
     if (fits) {
       if constexpr (sizeof(T) == 4) {
-        if (a.vec) return launch_larfb_reg<T, KT, IB, NW, true>(a, st);
+        if (a.prec == 2) return a.vec ? launch_larfb_reg<T, KT, IB, NW, true, 2>(a, st)
+                                      : launch_larfb_reg<T, KT, IB, NW, false, 2>(a, st);
+        if (a.prec == 3) return a.vec ? launch_larfb_reg<T, KT, IB, NW, true, 3>(a, st)
+                                      : launch_larfb_reg<T, KT, IB, NW, false, 3>(a, st);
+        if (a.vec) return launch_larfb_reg<T, KT, IB, NW, true, 0>(a, st);
       }
-      return launch_larfb_reg<T, KT, IB, NW, false>(a, st);
+      if (a.prec != 0) return hipErrorInvalidValue;
+      return launch_larfb_reg<T, KT, IB, NW, false, 0>(a, st);
     }
   }
+  if (a.prec != 0) return hipErrorInvalidValue;  // reduced precision only in the register-strip form
   if constexpr (larfb_stream_valid<T>(KT, IB, NW)) {
     return launch_larfb_stream<T, KT, IB, NW>(a, st);
   } else {

@@ -70,3 +70,12 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(svdv, "_lib", None)
     with pytest.raises(RuntimeError):
         svdv.lib()
+
+
+def test_reduced_precision_config_rules():
+    ok = svdv.Config(tile=16, threads=1024, inner_block=1, sweep_width=4, update_precision=2)
+    assert svdv.check_config(512, 512, "float32", ok)
+    assert svdv.check_config(512, 512, "float32", svdv.Config(16, 1024, 1, 4, 3))
+    assert not svdv.check_config(512, 512, "float64", ok)  # float32 input only
+    assert not svdv.check_config(512, 512, "float32", svdv.Config(16, 1024, 1, 4, 1))  # no such precision
+    assert not svdv.check_config(512, 512, "float32", svdv.Config(16, 256, 2, 4, 2))  # streaming-only configuration
