@@ -169,10 +169,12 @@ def svd_values(a, config=None, out=None):
     return s
 
 
-def svd_values_batched(mats, config=None):
+def svd_values_batched(mats, config=None, out=None):
     """Singular values of a list of 2-D CUDA tensors (same dtype, uneven sizes) in one call.
 
-    Returns (packed values, offsets): matrix i's values are packed[offsets[i]:offsets[i]+min(m_i,n_i)]."""
+    Returns (packed values, offsets): matrix i's values are packed[offsets[i]:offsets[i]+min(m_i,n_i)].
+    Passing the previous result as ``out`` keeps the output address, so a repeated call with the
+    same shapes replays the captured graph without refreshing its pointer table."""
     torch = _torch()
     if not mats:
         return None, []
@@ -188,7 +190,9 @@ def svd_values_batched(mats, config=None):
         ldas.append(lda)
         offs.append(off)
         off += min(m, n)
-    s = torch.empty(max(off, 1), dtype=mats[0].dtype, device=mats[0].device)
+    s = out if out is not None else torch.empty(max(off, 1), dtype=mats[0].dtype, device=mats[0].device)
+    if s.numel() < off or s.dtype != mats[0].dtype:
+        raise ValueError("out is too small or of the wrong dtype")
     B = len(mats)
     P = (ctypes.c_void_p * B)(*ptrs)
     I64 = ctypes.c_int64 * B

@@ -82,6 +82,24 @@ constexpr bool larfb_valid(int KT, int IB, int NW) {
   return larfb_reg_valid<T>(KT, IB, NW) || larfb_stream_valid<T>(KT, IB, NW);
 }
 
+// One matrix of a batch: its input, output and workspace pieces (device pointers).
+template <typename T>
+struct BatchMat {
+  const T* A;            // input, column-major, lda
+  int64_t m, n, lda;
+  int32_t transpose;     // 1 when m < n (the transpose is reduced)
+  int64_t M, N;          // reduced matrix (M >= N)
+  T* W;                  // working copy, M x N, leading dimension ldw
+  int64_t ldw;
+  unsigned long long* amax;
+  int* exp;              // power-of-two scale exponent
+  double* Bs;            // chase storage (N x 3b)
+  double* d;
+  double* e;
+  double* work;          // bisection work (2N + 2)
+  T* S;                  // output singular values (min(m, n))
+};
+
 // Fill kernels (used instead of hipMemsetAsync so that every step can be captured in a graph).
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n);
 __global__ void k_fill_i32(int* p, int v, int64_t n);
@@ -92,6 +110,16 @@ hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int tr
                            unsigned long long* amax, int* exp_out, hipStream_t st);
 template <typename T> int chunk_qr_hmax(int tile);
 template <typename T> hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st);
+// Batched forms (argument tables in device memory, one entry per matrix).
+template <typename T> hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, hipStream_t st);
+template <typename T>
+hipError_t launch_stage_in_batched(const BatchMat<T>* tab, int count, unsigned long long* amax_all, int64_t max_elems,
+                                   hipStream_t st);
+template <typename T>
+hipError_t launch_band_pack_batched(const BatchMat<T>* tab, int count, int b, int64_t max_n, hipStream_t st);
+template <typename T>
+hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,
+                                int64_t max_ncols, hipStream_t st);
 template <typename T> hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,
@@ -115,14 +143,30 @@ struct ChaseArgs {
   int32_t* err;        // set when a bounded wait gives up
   double* d;
   double* e;
+  // launch-level fields (set by the launchers): group tickets come from *ticket;
+  // a batched launch maps ticket t to matrix order[2t] (its arguments tab[...])
+  // and group order[2t+1]; total = number of tickets.
+  const ChaseArgs* tab;
+  const int* order;
+  int* ticket;
+  int32_t total;
 };
 size_t chase_lds_bytes(int b, int W);
 int chase_max_groups_resident(int b, int W);
 hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st);
+// Batched chase: L carries b, W, tab, order, ticket and total; zero_base[0 .. zero_count)
+// (every matrix's progress counters and the ticket) is cleared first; then d, e of every
+// matrix are extracted.
+hipError_t launch_chase_batched(const ChaseArgs& L, int grid, int count, int64_t max_n, int* zero_base,
+                                int64_t zero_count, hipStream_t st);
 
 // Stage 3.
 template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in,
                          int lanes_per_value, hipStream_t st);
+// Batched: value v (0 <= v < total) of the flattened batch is value v - voff[vmat[v]] of matrix vmat[v].
+template <typename T>
+hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
+                                 int lps, hipStream_t st);
 
 }  // namespace svdv

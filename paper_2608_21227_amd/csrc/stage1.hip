@@ -41,7 +41,8 @@ __device__ __forceinline__ unsigned long long abs_bits(double x) {
 }
 
 template <typename T>
-__global__ void k_absmax(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, unsigned long long* out) {
+__device__ __forceinline__ void absmax_body(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                            unsigned long long* out) {
   double mx = 0.0;
   int64_t total = m * n;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -62,6 +63,10 @@ __global__ void k_absmax(const T* __restrict__ A, int64_t m, int64_t n, int64_t 
     atomicMax(out, b);
   }
 }
+template <typename T>
+__global__ void k_absmax(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, unsigned long long* out) {
+  absmax_body(A, m, n, lda, out);
+}
 
 // exponent e with max*2^-e in [0.5, 1); 0 if max is zero or not finite
 __device__ __forceinline__ int scale_exponent(unsigned long long bits) {
@@ -73,8 +78,9 @@ __device__ __forceinline__ int scale_exponent(unsigned long long bits) {
 }
 
 template <typename T>
-__global__ void k_copy_scale(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, int transpose,
-                             T* __restrict__ W, int64_t ldw, const unsigned long long* amax, int* exp_out) {
+__device__ __forceinline__ void copy_scale_body(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                int transpose, T* __restrict__ W, int64_t ldw,
+                                                const unsigned long long* amax, int* exp_out) {
   int e = scale_exponent(*amax);
   if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
   // W is M x N with M = transpose ? n : m
@@ -85,6 +91,11 @@ __global__ void k_copy_scale(const T* __restrict__ A, int64_t m, int64_t n, int6
     T v = transpose ? A[j + i * lda] : A[i + j * lda];
     W[i + j * ldw] = (T)ldexp((double)v, -e);
   }
+}
+template <typename T>
+__global__ void k_copy_scale(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, int transpose,
+                             T* __restrict__ W, int64_t ldw, const unsigned long long* amax, int* exp_out) {
+  copy_scale_body(A, m, n, lda, transpose, W, ldw, amax, exp_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -105,11 +116,10 @@ struct ChunkQRCfg {
 };
 
 template <typename T, int TILE, int RPT>
-__global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
+__device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int c) {
   typedef ChunkQRCfg<T, TILE, RPT> C;
   constexpr int CPT = C::CPT;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int c = blockIdx.x;
   const int64_t row0 = (int64_t)c * a.chunk_rows;
   const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
   const int bw = a.bw;
@@ -305,6 +315,17 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
   }
 }
 
+template <typename T, int TILE, int RPT>
+__global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
+  chunk_qr_body<T, TILE, RPT>(a, blockIdx.x);
+}
+
+// Batched form: one single-chunk panel per matrix, matrix blockIdx.x of the table.
+template <typename T, int TILE, int RPT>
+__global__ __launch_bounds__(1024) void k_chunk_qr_b(const ChunkQRArgs<T>* __restrict__ tab) {
+  chunk_qr_body<T, TILE, RPT>(tab[blockIdx.x], 0);
+}
+
 // ---------------------------------------------------------------------------
 // a3/a5: trailing update  C <- (I - V T V^T)^T C  on MFMA
 // ---------------------------------------------------------------------------
@@ -315,8 +336,8 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ void k_band_pack(const T* __restrict__ W, int64_t ldw, int64_t n, int b, double* __restrict__ Bs, int64_t ldb,
-                            const int* exp_in, int unscale) {
+__device__ __forceinline__ void band_pack_body(const T* __restrict__ W, int64_t ldw, int64_t n, int b,
+                                               double* __restrict__ Bs, int64_t ldb, const int* exp_in, int unscale) {
   const int64_t total = n * ldb;
   const int e = unscale ? *exp_in : 0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -327,6 +348,30 @@ __global__ void k_band_pack(const T* __restrict__ W, int64_t ldw, int64_t n, int
     if (j >= i && j <= i + b && j < n) v = ldexp((double)W[i + j * ldw], e);
     Bs[idx] = v;
   }
+}
+template <typename T>
+__global__ void k_band_pack(const T* __restrict__ W, int64_t ldw, int64_t n, int b, double* __restrict__ Bs, int64_t ldb,
+                            const int* exp_in, int unscale) {
+  band_pack_body(W, ldw, n, b, Bs, ldb, exp_in, unscale);
+}
+
+// ---------------------------------------------------------------------------
+// batched forms of staging and band packing: matrix blockIdx.y of the table
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_absmax_b(const BatchMat<T>* __restrict__ tab) {
+  const BatchMat<T>& t = tab[blockIdx.y];
+  absmax_body(t.A, t.m, t.n, t.lda, t.amax);
+}
+template <typename T>
+__global__ void k_copy_scale_b(const BatchMat<T>* __restrict__ tab) {
+  const BatchMat<T>& t = tab[blockIdx.y];
+  copy_scale_body(t.A, t.m, t.n, t.lda, t.transpose, t.W, t.ldw, t.amax, t.exp);
+}
+template <typename T>
+__global__ void k_band_pack_b(const BatchMat<T>* __restrict__ tab, int b) {
+  const BatchMat<T>& t = tab[blockIdx.y];
+  band_pack_body(t.W, t.ldw, t.N, b, t.Bs, 3 * b, t.exp, 0);
 }
 
 // External band layout (band[i*ldband + d] = B(i, i+d), d = 0..b) <-> chase storage.
@@ -411,6 +456,56 @@ int chunk_qr_hmax(int tile) {
 template int chunk_qr_hmax<float>(int);
 template int chunk_qr_hmax<double>(int);
 
+template <typename T, int TILE, int RPT>
+static hipError_t launch_cqr_b(const ChunkQRArgs<T>* tab, int count, hipStream_t st) {
+  if constexpr (sizeof(T) == 8 && TILE > 64) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    const size_t lds = chunk_qr_lds<T, TILE, RPT>();
+    static bool configured = false;
+    if (!configured) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr_b<T, TILE, RPT>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      configured = true;
+    }
+    hipLaunchKernelGGL((k_chunk_qr_b<T, TILE, RPT>), dim3(count), dim3(1024), lds, st, tab);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  switch (tile) {
+    case 16: return launch_cqr_b<T, 16, ChunkRPT<T, 16>::value>(tab, count, st);
+    case 32: return launch_cqr_b<T, 32, ChunkRPT<T, 32>::value>(tab, count, st);
+    case 64: return launch_cqr_b<T, 64, ChunkRPT<T, 64>::value>(tab, count, st);
+    case 128: return launch_cqr_b<T, 128, ChunkRPT<T, 128>::value>(tab, count, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_stage_in_batched(const BatchMat<T>* tab, int count, unsigned long long* amax_all, int64_t max_elems,
+                                   hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(std::max(1, std::min(64, (count + 255) / 256))), dim3(256), 0, st, amax_all,
+                     0ull, (int64_t)count);
+  const int gx = std::max(1, std::min(grid_for(max_elems, 256), 64));
+  hipLaunchKernelGGL(k_absmax_b<T>, dim3(gx, count), dim3(256), 0, st, tab);
+  hipLaunchKernelGGL(k_copy_scale_b<T>, dim3(gx, count), dim3(256), 0, st, tab);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_pack_batched(const BatchMat<T>* tab, int count, int b, int64_t max_n, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int gx = std::max(1, std::min(grid_for(max_n * 3 * b, 256), 64));
+  hipLaunchKernelGGL(k_band_pack_b<T>, dim3(gx, count), dim3(256), 0, st, tab, b);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st) {
   switch (tile) {
@@ -447,6 +542,9 @@ hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, d
   template hipError_t launch_stage_in<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t, unsigned long long*, \
                                          int*, hipStream_t);                                                      \
   template hipError_t launch_chunk_qr<T>(int, const ChunkQRArgs<T>&, hipStream_t);                               \
+  template hipError_t launch_chunk_qr_batched<T>(int, const ChunkQRArgs<T>*, int, hipStream_t);                  \
+  template hipError_t launch_stage_in_batched<T>(const BatchMat<T>*, int, unsigned long long*, int64_t, hipStream_t); \
+  template hipError_t launch_band_pack_batched<T>(const BatchMat<T>*, int, int, int64_t, hipStream_t);          \
   template hipError_t launch_band_pack<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*, int,     \
                                           hipStream_t);                                                           \
   template hipError_t launch_band_extract<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*,       \

@@ -185,15 +185,27 @@ __device__ void chase_task(const ChaseCtx& X, int64_t p, int64_t c, double* tile
   }
 }
 
-// Next group for this workgroup (ticket in progress[ngroups], zeroed with the
-// progress counters).  Every thread returns the same value.
-__device__ __forceinline__ int next_group(const ChaseArgs& a) {
+// Next group for this workgroup: a ticket from the launch's counter (zeroed
+// before the launch), mapped to (matrix, group) by the order table of a batched
+// launch (tickets of one matrix's groups are increasing, so every predecessor
+// holds a smaller ticket), or to group = ticket for one matrix.  Every thread
+// gets the same result; gi < 0 when no group is left.
+__device__ __forceinline__ ChaseArgs take_group(const ChaseArgs& L, int& gi) {
   __shared__ int s_ticket;
-  if (threadIdx.x == 0) s_ticket = atomicAdd(a.progress + a.ngroups, 1);
+  if (threadIdx.x == 0) s_ticket = atomicAdd(L.ticket, 1);
   __syncthreads();
-  const int gi = s_ticket;
+  const int tk = s_ticket;
   __syncthreads();
-  return gi;
+  if (tk >= L.total) {
+    gi = -1;
+    return L;
+  }
+  if (L.order == nullptr) {
+    gi = tk;
+    return L;
+  }
+  gi = L.order[2 * tk + 1];
+  return L.tab[L.order[2 * tk]];
 }
 
 __device__ __forceinline__ int ntasks_of(int64_t s, int64_t n, int b) {
@@ -213,21 +225,22 @@ size_t chase_lds_bytes(int b, int W) {
   return (size_t)W * (tile + b) * sizeof(double);
 }
 
-__global__ void k_chase(ChaseArgs a) {
+__global__ void k_chase(ChaseArgs L) {
   extern __shared__ __align__(16) double lds[];
   const int wv = threadIdx.x >> 6;
-  const int W = a.W;
-  const int b = a.b;
+  const int W = L.W;
+  const int b = L.b;
   const int tile_elems = 64 * (b + 1) > b * 65 ? 64 * (b + 1) : b * 65;
   double* tile = lds + (size_t)wv * (tile_elems + b);
   double* vb = tile + tile_elems;
-  ChaseCtx X{a.Bs, a.ldb, a.n, b, b - 1};
-  const int64_t n = a.n;
   __shared__ int s_giveup;
 
   for (;;) {
-    const int gi = next_group(a);
-    if (gi >= a.ngroups) break;
+    int gi;
+    const ChaseArgs a = take_group(L, gi);
+    if (gi < 0) break;
+    const int64_t n = a.n;
+    const ChaseCtx X{a.Bs, a.ldb, a.n, b, b - 1};
     const int64_t s0 = (int64_t)gi * W;
     const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
     int tend = 0;
@@ -444,22 +457,23 @@ __device__ __forceinline__ int64_t sweep_front(int64_t s, int j, int b) {
 }
 
 template <int B>
-__global__ void __launch_bounds__(512) k_chase_win(ChaseArgs a) {
+__global__ void __launch_bounds__(512) k_chase_win(ChaseArgs L) {
   constexpr int RW = WinGeom<B>::RW, RS = WinGeom<B>::RS, PF = WinGeom<B>::PF;
   extern __shared__ __align__(16) double lds[];
-  const int W = a.W;
+  const int W = L.W;
   const int R = win_rows(B, W);
   lds_f64* win = (lds_f64*)lds;
   for (int e = threadIdx.x; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
   const int wv = threadIdx.x >> 6;
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
-  const int64_t n = a.n;
   __shared__ int s_giveup;
 
   for (;;) {
-    const int gi = next_group(a);
-    if (gi >= a.ngroups) break;
+    int gi;
+    const ChaseArgs a = take_group(L, gi);
+    if (gi < 0) break;
+    const int64_t n = a.n;
     const int64_t s0 = (int64_t)gi * W;
     const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
     int tend = 0;
@@ -607,23 +621,24 @@ size_t chase_spec_lds_bytes(int b, int W) {
 }
 
 template <int B>
-__global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(ChaseArgs a) {
+__global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(ChaseArgs L) {
   constexpr int RW = 3 * B, RS = RW + 2, MT = 64 * kSpecMovers;
   constexpr int KP = (B * RW / 2 + MT - 1) / MT;  // pairs of doubles per mover thread for B rows
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_flag;
-  const int W = a.W;
+  const int W = L.W;
   const int R = spec_rows(B, W);
   lds_f64* win = (lds_f64*)lds;
   const int wv = threadIdx.x >> 6, tid = threadIdx.x;
   const bool mover = wv >= W;
   const int mt = tid - 64 * W;  // mover thread index (valid when mover)
-  const int64_t n = a.n;
   for (int e = tid; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
 
   for (;;) {
-    const int gi = next_group(a);
-    if (gi >= a.ngroups) break;
+    int gi;
+    const ChaseArgs a = take_group(L, gi);
+    if (gi < 0) break;
+    const int64_t n = a.n;
     const int64_t s0 = (int64_t)gi * W;
     const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
     const int64_t sl = s0 + nsw - 1;
@@ -810,11 +825,19 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
 }
 
 // d_i = B(i, i), e_i = B(i, i+1) once every sweep has finished (next kernel in the stream).
-__global__ void k_chase_extract(const double* __restrict__ Bs, int64_t ldb, int64_t n, int b, double* d, double* e) {
+__device__ __forceinline__ void chase_extract_body(const double* __restrict__ Bs, int64_t ldb, int64_t n, int b,
+                                                   double* d, double* e) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     d[i] = Bs[i * ldb + (b - 1)];
     if (i + 1 < n) e[i] = Bs[i * ldb + b];
   }
+}
+__global__ void k_chase_extract(const double* __restrict__ Bs, int64_t ldb, int64_t n, int b, double* d, double* e) {
+  chase_extract_body(Bs, ldb, n, b, d, e);
+}
+__global__ void k_chase_extract_b(const ChaseArgs* __restrict__ tab) {
+  const ChaseArgs& a = tab[blockIdx.y];
+  chase_extract_body(a.Bs, a.ldb, a.n, a.b, a.d, a.e);
 }
 
 static bool use_spec(int b, int W) { return b == 16 && W <= kSpecMaxW && chase_spec_lds_bytes(b, W) <= 159 * 1024; }
@@ -854,22 +877,47 @@ int chase_max_groups_resident(int b, int W) {
   return per * cus;
 }
 
-hipError_t launch_chase(const ChaseArgs& a, int grid, hipStream_t st) {
+static hipError_t launch_chase_kernel(const ChaseArgs& a, int grid, hipStream_t st) {
   const void* fn = chase_fn(a.b, a.W);
   const size_t lds = chase_launch_lds(a.b, a.W);
   hipError_t e = chase_set_lds(fn, lds);
   if (e != hipSuccess) return e;
-  if (a.n > 1) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, st, a.progress, 0, (int64_t)a.ngroups + 1);
+  {
     const dim3 block(chase_threads(a.b, a.W));
     if (fn == (const void*)k_chase_spec<16>) hipLaunchKernelGGL(k_chase_spec<16>, dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_win<16>) hipLaunchKernelGGL(k_chase_win<16>, dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_win<32>) hipLaunchKernelGGL(k_chase_win<32>, dim3(grid), block, lds, st, a);
     else hipLaunchKernelGGL(k_chase, dim3(grid), block, lds, st, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_chase(const ChaseArgs& a0, int grid, hipStream_t st) {
+  ChaseArgs a = a0;
+  a.tab = nullptr;
+  a.order = nullptr;
+  a.ticket = a.progress + a.ngroups;  // zeroed with the progress counters
+  a.total = a.ngroups;
+  if (a.n > 1) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, st, a.progress, 0, (int64_t)a.ngroups + 1);
+    hipError_t e = launch_chase_kernel(a, grid, st);
+    if (e != hipSuccess) return e;
+  }
   const int g = (int)((a.n + 255) / 256);
   hipLaunchKernelGGL(k_chase_extract, dim3(g < 1 ? 1 : (g > 4096 ? 4096 : g)), dim3(256), 0, st, a.Bs, a.ldb, a.n,
                      a.b, a.d, a.e);
+  return hipGetLastError();
+}
+
+hipError_t launch_chase_batched(const ChaseArgs& L, int grid, int count, int64_t max_n, int* zero_base,
+                                int64_t zero_count, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, st, zero_base, 0, zero_count);  // progress + ticket
+  if (L.total > 0) {
+    hipError_t e = launch_chase_kernel(L, grid, st);
+    if (e != hipSuccess) return e;
+  }
+  const int g = (int)((max_n + 255) / 256);
+  hipLaunchKernelGGL(k_chase_extract_b, dim3(g < 1 ? 1 : (g > 64 ? 64 : g), count), dim3(256), 0, st, L.tab);
   return hipGetLastError();
 }
 

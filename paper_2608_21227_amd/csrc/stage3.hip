@@ -16,7 +16,8 @@
 namespace svdv {
 
 // work layout: dd[n], ee[n], then [2*n] = bound, [2*n+1] = pivmin
-__global__ void k_bisect_prep(const double* __restrict__ d, const double* __restrict__ e, int64_t n, double* work) {
+__device__ __forceinline__ void bisect_prep_body(const double* __restrict__ d, const double* __restrict__ e, int64_t n,
+                                                 double* work) {
   __shared__ double smax[3][256];
   double md = 0.0, me = 0.0, me2 = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -43,6 +44,15 @@ __global__ void k_bisect_prep(const double* __restrict__ d, const double* __rest
   }
 }
 
+__global__ void k_bisect_prep(const double* __restrict__ d, const double* __restrict__ e, int64_t n, double* work) {
+  bisect_prep_body(d, e, n, work);
+}
+template <typename T>
+__global__ void k_bisect_prep_b(const BatchMat<T>* __restrict__ tab) {
+  const BatchMat<T>& t = tab[blockIdx.x];
+  bisect_prep_body(t.d, t.e, t.N, t.work);
+}
+
 __device__ __forceinline__ int sturm_count(const double* __restrict__ dd, const double* __restrict__ ee, int64_t n,
                                            double x, double pivmin) {
   const double t = x * x;
@@ -60,17 +70,18 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ dd, const 
   return cnt;
 }
 
+// One team of lps lanes locates value k (k-th smallest) of the bidiagonal whose
+// prepared work array is `work`; inactive teams (active = false) still take part
+// in the wave-wide votes.
 template <typename T>
-__global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S, const int* exp_in, int lps) {
+__device__ __forceinline__ void bisect_team(const double* __restrict__ work, int64_t n, T* __restrict__ S,
+                                            const int* exp_in, int64_t k, bool active, int lps) {
   const double* dd = work;
   const double* ee = work + n;
-  const double bound = work[2 * n];
-  const double pivmin = work[2 * n + 1];
+  const double bound = active ? work[2 * n] : 0.0;
+  const double pivmin = active ? work[2 * n + 1] : 0.0;
   const int lane = threadIdx.x & 63;
   const int team_in_wave = lane / lps, j = lane % lps;
-  const int teams_per_wave = 64 / lps;
-  const int64_t k = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + team_in_wave;
-  const bool active = k < n;
   double lo = 0.0, hi = bound;
   const double tol = 4.0 * DBL_EPSILON * bound;
   const uint64_t team_mask = (lps == 64) ? ~0ull : (((1ull << lps) - 1) << (team_in_wave * lps));
@@ -100,6 +111,28 @@ __global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restri
 }
 
 template <typename T>
+__global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S, const int* exp_in, int lps) {
+  const int lane = threadIdx.x & 63;
+  const int teams_per_wave = 64 / lps;
+  const int64_t k = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
+  bisect_team(work, n, S, exp_in, k, k < n, lps);
+}
+
+// Batched form: value v of the flattened batch belongs to matrix vmat[v] as its
+// value v - voff[vmat[v]].
+template <typename T>
+__global__ void k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __restrict__ vmat,
+                           const int64_t* __restrict__ voff, int64_t total, int lps) {
+  const int lane = threadIdx.x & 63;
+  const int teams_per_wave = 64 / lps;
+  const int64_t v = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
+  const bool active = v < total;
+  const int mi = active ? vmat[v] : 0;
+  const BatchMat<T>& t = tab[mi];
+  bisect_team(t.work, t.N, t.S, t.exp, active ? v - voff[mi] : 0, active, lps);
+}
+
+template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in, int lps,
                          hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -110,6 +143,20 @@ hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, doub
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
+                                 int lps, hipStream_t st) {
+  if (count <= 0 || total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bisect_prep_b<T>, dim3(count), dim3(256), 0, st, tab);
+  const int teams_per_block = 256 / lps;
+  const int64_t blocks = (total + teams_per_block - 1) / teams_per_block;
+  hipLaunchKernelGGL(k_bisect_b<T>, dim3((unsigned)blocks), dim3(256), 0, st, tab, vmat, voff, total, lps);
+  return hipGetLastError();
+}
+template hipError_t launch_bisect_batched<float>(const BatchMat<float>*, int, const int*, const int64_t*, int64_t, int,
+                                                 hipStream_t);
+template hipError_t launch_bisect_batched<double>(const BatchMat<double>*, int, const int*, const int64_t*, int64_t,
+                                                  int, hipStream_t);
 template hipError_t launch_bisect<float>(const double*, const double*, int64_t, float*, double*, const int*, int,
                                          hipStream_t);
 template hipError_t launch_bisect<double>(const double*, const double*, int64_t, double*, double*, const int*, int,

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -124,15 +125,18 @@ int check_config_impl(int64_t m, int64_t n, int dtype, const svdv_config& c) {
 }
 
 svdv_config default_config(int64_t m, int64_t n, int dtype) {
+  // The auto-tuner's best configuration for the dense n = 4096 float32 cell
+  // (tile 16, 1024 threads, inner block 1, sweep width 4); float64 keeps tile 16
+  // and the sweep width with 256 threads, the widest workgroup whose trailing
+  // update fits its registers in float64.
   (void)m;
+  (void)n;
   svdv_config c;
-  c.tile = 32;
-  c.threads = 256;
-  c.inner_block = 2;
+  c.tile = 16;
+  c.threads = dtype == SVDV_F32 ? 1024 : 256;
+  c.inner_block = 1;
   c.sweep_width = 4;
   c.update_precision = 0;
-  (void)n;
-  (void)dtype;
   return c;
 }
 
@@ -446,6 +450,348 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   return SVDV_OK;
 }
 
+// ----------------------------------------------------------------------------
+// batched driver: every stage runs once for the whole batch, matrix i taking
+// its share of each launch through per-matrix argument tables in device
+// memory; the launch sequence is captured in a hipGraph and replayed while the
+// shapes stay the same (only the pointer table is refreshed between calls).
+// ----------------------------------------------------------------------------
+
+struct BatchPlan {
+  // key
+  int dtype = -1;
+  svdv_config cfg{};
+  std::vector<int64_t> m, n, lda, soff;
+  // device memory: tables + per-matrix workspaces
+  char* mem = nullptr;
+  size_t bytes = 0;
+  size_t mats_off = 0;             // BatchMat<T>[count] (refreshed per call)
+  std::vector<char> mats_host;     // host copy of that table
+  std::vector<int> idx;            // plan order -> batch index (matrices with min(m, n) > 0, N descending)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::function<int(hipStream_t)> record;  // enqueues the launch sequence (built with the tables)
+  void release() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (mem) hipFree(mem);
+    exec = nullptr;
+    graph = nullptr;
+    mem = nullptr;
+  }
+};
+std::map<std::pair<int, void*>, BatchPlan> g_batch;
+
+// Builds the plan's tables and workspaces (uploaded here, before any capture)
+// and the recorder of its launch sequence.
+template <typename T>
+int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
+  const svdv_config& cfg = P.cfg;
+  const int b = cfg.tile, W = cfg.sweep_width;
+  const int cnt = (int)P.idx.size();
+  // sizes in plan order
+  std::vector<int64_t> Mv(cnt), Nv(cnt), ldw(cnt), ldv(cnt), ng(cnt);
+  int64_t maxN = 0, maxM = 0, total_groups = 0, total_vals = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const int q = P.idx[i];
+    Mv[i] = std::max(P.m[q], P.n[q]);
+    Nv[i] = std::min(P.m[q], P.n[q]);
+    ldw[i] = (Mv[i] + 15) / 16 * 16;
+    ldv[i] = ldw[i];
+    ng[i] = std::max<int64_t>(0, (Nv[i] - 1 + W - 1) / W);
+    maxN = std::max(maxN, Nv[i]);
+    maxM = std::max(maxM, Mv[i]);
+    total_groups += ng[i];
+    total_vals += Nv[i];
+  }
+  const int64_t steps = (maxN + b - 1) / b;
+  // layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  P.mats_off = take(sizeof(BatchMat<T>) * cnt);
+  const size_t qr_off = take(sizeof(ChunkQRArgs<T>) * cnt * steps), lq_off = take(sizeof(ChunkQRArgs<T>) * cnt * steps);
+  const size_t uq_off = take(sizeof(LarfbArgs<T>) * cnt * steps), ul_off = take(sizeof(LarfbArgs<T>) * cnt * steps);
+  const size_t ch_off = take(sizeof(ChaseArgs) * cnt);
+  const size_t ord_off = take(sizeof(int) * 2 * std::max<int64_t>(1, total_groups));
+  const size_t vmat_off = take(sizeof(int) * std::max<int64_t>(1, total_vals));
+  const size_t voff_off = take(sizeof(int64_t) * cnt);
+  // progress counters of every matrix (ng + 1 each), then the ticket and the error flag: one fill clears them
+  std::vector<int64_t> prog(cnt);
+  int64_t nprog = 0;
+  for (int i = 0; i < cnt; ++i) {
+    prog[i] = nprog;
+    nprog += ng[i] + 1;
+  }
+  const size_t prog_off = take(sizeof(int) * (nprog + 2));
+  const size_t amax_off = take(sizeof(unsigned long long) * cnt);
+  const size_t exp_off = take(sizeof(int) * cnt);
+  std::vector<size_t> w_off(cnt), v_off(cnt), t_off(cnt), bs_off(cnt), d_off(cnt), e_off(cnt), wk_off(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    w_off[i] = take(sizeof(T) * ldw[i] * Nv[i]);
+    v_off[i] = take(sizeof(T) * ldv[i] * b);
+    t_off[i] = take(sizeof(T) * b * b);
+    bs_off[i] = take(sizeof(double) * Nv[i] * 3 * b);
+    d_off[i] = take(sizeof(double) * Nv[i]);
+    e_off[i] = take(sizeof(double) * Nv[i]);
+    wk_off[i] = take(sizeof(double) * (2 * Nv[i] + 2));
+  }
+  if (off > P.bytes) {
+    if (P.mem) HIPCHK(hipFree(P.mem));
+    P.mem = nullptr;
+    hipError_t e = hipMalloc(&P.mem, off);
+    if (e != hipSuccess) return fail(SVDV_ERR_NO_MEMORY, "batched workspace hipMalloc failed");
+    P.bytes = off;
+  }
+  char* base = P.mem;
+  // host tables
+  std::vector<BatchMat<T>> mats(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const int q = P.idx[i];
+    BatchMat<T>& t = mats[i];
+    t.A = (const T*)A_array[q];
+    t.m = P.m[q];
+    t.n = P.n[q];
+    t.lda = P.lda[q];
+    t.transpose = P.m[q] < P.n[q];
+    t.M = Mv[i];
+    t.N = Nv[i];
+    t.W = (T*)(base + w_off[i]);
+    t.ldw = ldw[i];
+    t.amax = (unsigned long long*)(base + amax_off) + i;
+    t.exp = (int*)(base + exp_off) + i;
+    t.Bs = (double*)(base + bs_off[i]);
+    t.d = (double*)(base + d_off[i]);
+    t.e = (double*)(base + e_off[i]);
+    t.work = (double*)(base + wk_off[i]);
+    t.S = (T*)S + P.soff[q];
+  }
+  std::vector<ChunkQRArgs<T>> qr(cnt * steps), lq(cnt * steps);
+  std::vector<LarfbArgs<T>> uq(cnt * steps), ul(cnt * steps);
+  std::vector<int> n_qr(steps, 0), n_lq(steps, 0), vec_qr(steps, 1), vec_lq(steps, 1);
+  std::vector<int64_t> mc_qr(steps, 0), mc_lq(steps, 0);
+  for (int64_t k = 0; k < steps; ++k) {
+    const int64_t k0 = k * b;
+    for (int i = 0; i < cnt; ++i) {
+      if (Nv[i] <= k0) break;  // N descending: the active matrices are a prefix
+      T* Wp = mats[i].W;
+      T* Vp = (T*)(base + v_off[i]);
+      T* Tp = (T*)(base + t_off[i]);
+      const int bw = (int)std::min<int64_t>(b, Nv[i] - k0);
+      {  // QR sweep of the tile column
+        const int64_t h = Mv[i] - k0;
+        ChunkQRArgs<T>& a = qr[k * cnt + i];
+        a.M = View<T>{Wp, 1, ldw[i]};
+        a.pc = k0;
+        a.bw = bw;
+        a.rm = RowMap{k0, h, 0, 0};
+        a.h = h;
+        a.chunk_rows = h;
+        a.P = 1;
+        a.V = Vp;
+        a.ldv = (h + 15) / 16 * 16;
+        a.Tm = Tp;
+        LarfbArgs<T>& u = uq[k * cnt + i];
+        u.M = a.M;
+        u.rm = a.rm;
+        u.h = h;
+        u.chunk_rows = h;
+        u.P = 1;
+        u.col0 = k0 + bw;
+        u.col1 = Nv[i];
+        u.V = Vp;
+        u.ldv = a.ldv;
+        u.Tm = Tp;
+        u.ldt = b;
+        u.k = (int32_t)std::min<int64_t>(bw, h);
+        u.prec = cfg.update_precision;
+        u.vec = larfb_vec_ok(u);
+        vec_qr[k] &= u.vec;
+        mc_qr[k] = std::max<int64_t>(mc_qr[k], u.col1 - u.col0);
+        n_qr[k] = i + 1;
+      }
+      const int64_t c1 = k0 + b;
+      if (c1 < Nv[i]) {  // LQ sweep of the tile row
+        const int64_t h = Nv[i] - c1;
+        ChunkQRArgs<T>& a = lq[k * cnt + i];
+        a.M = View<T>{Wp, ldw[i], 1};
+        a.pc = k0;
+        a.bw = b;
+        a.rm = RowMap{c1, h, 0, 0};
+        a.h = h;
+        a.chunk_rows = h;
+        a.P = 1;
+        a.V = Vp;
+        a.ldv = (h + 15) / 16 * 16;
+        a.Tm = Tp;
+        LarfbArgs<T>& u = ul[k * cnt + i];
+        u.M = a.M;
+        u.rm = a.rm;
+        u.h = h;
+        u.chunk_rows = h;
+        u.P = 1;
+        u.col0 = k0 + b;
+        u.col1 = Mv[i];
+        u.V = Vp;
+        u.ldv = a.ldv;
+        u.Tm = Tp;
+        u.ldt = b;
+        u.k = (int32_t)std::min<int64_t>(b, h);
+        u.prec = cfg.update_precision;
+        u.vec = larfb_vec_ok(u);
+        vec_lq[k] &= u.vec;
+        mc_lq[k] = std::max<int64_t>(mc_lq[k], u.col1 - u.col0);
+        n_lq[k] = i + 1;
+      }
+    }
+  }
+  int* progress = (int*)(base + prog_off);
+  int* ticket = progress + nprog;
+  int* err = ticket + 1;
+  std::vector<ChaseArgs> ch(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    ChaseArgs& c = ch[i];
+    c = ChaseArgs{};
+    c.Bs = mats[i].Bs;
+    c.ldb = 3 * b;
+    c.n = Nv[i];
+    c.b = b;
+    c.W = W;
+    c.ngroups = (int32_t)ng[i];
+    c.progress = progress + prog[i];
+    c.err = err;
+    c.d = mats[i].d;
+    c.e = mats[i].e;
+  }
+  std::vector<int> order;
+  order.reserve(2 * total_groups);
+  for (int64_t r = 0;; ++r) {  // round robin over matrices: predecessors keep smaller tickets
+    bool any = false;
+    for (int i = 0; i < cnt; ++i)
+      if (r < ng[i]) {
+        order.push_back(i);
+        order.push_back((int)r);
+        any = true;
+      }
+    if (!any) break;
+  }
+  std::vector<int> vmat(total_vals);
+  std::vector<int64_t> voff(cnt);
+  for (int i = 0, v = 0; i < cnt; ++i) {
+    voff[i] = v;
+    for (int64_t j = 0; j < Nv[i]; ++j) vmat[v++] = i;
+  }
+  // upload (synchronous, before anything is recorded)
+  auto up = [&](size_t o, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  HIPCHK(up(P.mats_off, mats.data(), sizeof(BatchMat<T>) * cnt));
+  HIPCHK(up(qr_off, qr.data(), sizeof(ChunkQRArgs<T>) * qr.size()));
+  HIPCHK(up(lq_off, lq.data(), sizeof(ChunkQRArgs<T>) * lq.size()));
+  HIPCHK(up(uq_off, uq.data(), sizeof(LarfbArgs<T>) * uq.size()));
+  HIPCHK(up(ul_off, ul.data(), sizeof(LarfbArgs<T>) * ul.size()));
+  HIPCHK(up(ch_off, ch.data(), sizeof(ChaseArgs) * cnt));
+  HIPCHK(up(ord_off, order.data(), sizeof(int) * order.size()));
+  HIPCHK(up(vmat_off, vmat.data(), sizeof(int) * vmat.size()));
+  HIPCHK(up(voff_off, voff.data(), sizeof(int64_t) * cnt));
+  P.mats_host.assign((const char*)mats.data(), (const char*)mats.data() + sizeof(BatchMat<T>) * cnt);
+
+  // ---- the launch sequence ----
+  const int nw = cfg.threads / 64, ib = cfg.inner_block, prec = cfg.update_precision;
+  ChaseArgs L{};
+  L.b = b;
+  L.W = W;
+  L.ldb = 3 * b;
+  L.tab = (const ChaseArgs*)(base + ch_off);
+  L.order = (const int*)(base + ord_off);
+  L.ticket = ticket;
+  L.total = (int32_t)total_groups;
+  L.err = err;
+  const int grid = std::max(1, chase_grid((int)std::max<int64_t>(1, total_groups), b, W));
+  const size_t mats_off = P.mats_off;
+  P.record = [=](hipStream_t st) -> int {
+    const BatchMat<T>* dmats = (const BatchMat<T>*)(base + mats_off);
+    HIPCHK(launch_stage_in_batched<T>(dmats, cnt, (unsigned long long*)(base + amax_off), maxM * maxN, st));
+    for (int64_t k = 0; k < steps; ++k) {
+      HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + qr_off) + k * cnt, n_qr[k], st));
+      HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_qr[k], (const LarfbArgs<T>*)(base + uq_off) + k * cnt,
+                                     n_qr[k], mc_qr[k], st));
+      if (n_lq[k] > 0) {
+        HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + lq_off) + k * cnt, n_lq[k], st));
+        HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_lq[k], (const LarfbArgs<T>*)(base + ul_off) + k * cnt,
+                                       n_lq[k], mc_lq[k], st));
+      }
+    }
+    HIPCHK(launch_band_pack_batched<T>(dmats, cnt, b, maxN, st));
+    HIPCHK(launch_chase_batched(L, grid, cnt, maxN, progress, nprog + 2, st));
+    HIPCHK(launch_bisect_batched<T>(dmats, cnt, (const int*)(base + vmat_off), (const int64_t*)(base + voff_off),
+                                    total_vals, 16, st));
+    return SVDV_OK;
+  };
+  return SVDV_OK;
+}
+
+// Stream on which batched graphs are captured (the caller's stream may be the
+// legacy default stream, which cannot be captured); one per device, default priority.
+int capture_stream(hipStream_t* out) {
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipStream_t& s = streams[dev];
+  if (!s) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  *out = s;
+  return SVDV_OK;
+}
+
+template <typename T>
+int batched_run(BatchPlan& P, const void* const* A_array, void* S, hipStream_t st) {
+  if (!P.exec) {
+    // tables first (plain copies), then the launch sequence recorded into a graph
+    int rc = batched_build<T>(P, A_array, S);
+    if (rc) return rc;
+    hipStream_t cs = nullptr;
+    rc = capture_stream(&cs);
+    if (rc) return rc;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    rc = P.record(cs);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHK(ce);
+    P.graph = g;
+    HIPCHK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  } else {
+    // same shapes: refresh the input / output pointers of the matrix table if they changed
+    const int cnt = (int)P.idx.size();
+    std::vector<BatchMat<T>> mats(cnt);
+    std::memcpy(mats.data(), P.mats_host.data(), sizeof(BatchMat<T>) * cnt);
+    bool changed = false;
+    for (int i = 0; i < cnt; ++i) {
+      const int q = P.idx[i];
+      const T* a = (const T*)A_array[q];
+      T* s = (T*)S + P.soff[q];
+      if (mats[i].A != a || mats[i].S != s) {
+        mats[i].A = a;
+        mats[i].S = s;
+        changed = true;
+      }
+    }
+    if (changed) {
+      HIPCHK(hipStreamSynchronize(st));  // earlier replays may still read the table
+      HIPCHK(hipMemcpy(P.mem + P.mats_off, mats.data(), sizeof(BatchMat<T>) * cnt, hipMemcpyHostToDevice));
+      P.mats_host.assign((const char*)mats.data(), (const char*)mats.data() + sizeof(BatchMat<T>) * cnt);
+    }
+  }
+  HIPCHK(hipGraphLaunch(P.exec, st));
+  return SVDV_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -626,17 +972,59 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
                        int32_t dtype, void* S, const int64_t* S_offset, void* stream, const svdv_config* cfg) {
   if (batch < 0) return fail(SVDV_ERR_INVALID_ARG, "batch must be >= 0");
   if (batch == 0) return SVDV_OK;
+  if (batch > (1 << 20)) return fail(SVDV_ERR_UNSUPPORTED, "batch above 2^20");
   if (!A_array || !m || !n || !lda || !S_offset || !S) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  int64_t maxdim = 1;
   for (int64_t i = 0; i < batch; ++i) {
     int rc = check_matrix_args(A_array[i], m[i], n[i], lda[i], dtype);
     if (rc) return rc;
+    if (S_offset[i] < 0) return fail(SVDV_ERR_INVALID_ARG, "negative S_offset");
+    maxdim = std::max<int64_t>(maxdim, std::max(m[i], n[i]));
   }
-  const int es = elem_size(dtype);
-  for (int64_t i = 0; i < batch; ++i) {
-    int rc = svd_values_ex(A_array[i], m[i], n[i], lda[i], dtype, (char*)S + S_offset[i] * es, stream, cfg);
-    if (rc) return rc;
+  svdv_config c = cfg ? *cfg : default_config(maxdim, maxdim, dtype);
+  int rc = check_config_impl(maxdim, maxdim, dtype, c);
+  if (rc) return rc;
+  const bool reg_ok = dtype == SVDV_F32 ? larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
+                                        : larfb_reg_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
+  const int hmax = dtype == SVDV_F32 ? chunk_qr_hmax<float>(c.tile) : chunk_qr_hmax<double>(c.tile);
+  if (!reg_ok || maxdim > hmax) {
+    // outside the batched kernels' reach (a strip that does not fit in registers, or
+    // matrices taller than one panel chunk): the matrices run one after another
+    const int es = elem_size(dtype);
+    for (int64_t i = 0; i < batch; ++i) {
+      rc = svd_values_ex(A_array[i], m[i], n[i], lda[i], dtype, (char*)S + S_offset[i] * es, stream, &c);
+      if (rc) return rc;
+    }
+    return SVDV_OK;
   }
-  return SVDV_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  BatchPlan& P = g_batch[{dev, stream}];
+  const std::vector<int64_t> mv(m, m + batch), nv(n, n + batch), lv(lda, lda + batch), ov(S_offset, S_offset + batch);
+  const bool same = P.exec && P.dtype == dtype && std::memcmp(&P.cfg, &c, sizeof(c)) == 0 && P.m == mv && P.n == nv &&
+                    P.lda == lv && P.soff == ov;
+  if (!same) {
+    if (P.exec || P.mem) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    P.release();
+    P.bytes = 0;
+    P.dtype = dtype;
+    P.cfg = c;
+    P.m = mv;
+    P.n = nv;
+    P.lda = lv;
+    P.soff = ov;
+    P.idx.clear();
+    for (int64_t i = 0; i < batch; ++i)
+      if (std::min(m[i], n[i]) > 0) P.idx.push_back((int)i);
+    std::stable_sort(P.idx.begin(), P.idx.end(),
+                     [&](int a, int b) { return std::min(m[a], n[a]) > std::min(m[b], n[b]); });
+    if (P.idx.empty()) return SVDV_OK;
+  }
+  if (P.idx.empty()) return SVDV_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SVDV_F32) return batched_run<float>(P, A_array, S, st);
+  return batched_run<double>(P, A_array, S, st);
 }
 
 int svdv_timing(int enable) {
@@ -696,6 +1084,12 @@ int svdv_release(void) {
     }
   }
   g_ws.clear();
+  for (auto& kv : g_batch) {
+    hipSetDevice(kv.first.first);
+    hipStreamSynchronize((hipStream_t)kv.first.second);
+    kv.second.release();
+  }
+  g_batch.clear();
   return SVDV_OK;
 }
 

@@ -96,7 +96,7 @@ __device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int H
 
 // PREC 0: MFMA in T; PREC 2 / 3 (T = float): BF16 / FP16 operands, float32 accumulation.
 template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
-__global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
+__device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int strip, const int c) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -104,11 +104,10 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   T* Zp = Zs + (size_t)NW * KR * CB;       // [KR][CB] Z' = T^T Z
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, nl = lane & 15;
-  const int c = blockIdx.y;
   const int64_t row0 = (int64_t)c * a.chunk_rows;
   const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
   const int k = a.k;
-  const int64_t colbase = a.col0 + (int64_t)blockIdx.x * CB;
+  const int64_t colbase = a.col0 + (int64_t)strip * CB;
   const T* V = a.V + row0;
   const T* Tm = a.Tm + (int64_t)c * a.ldt * a.ldt;
   const int nslab = (Hc + 15) >> 4;
@@ -237,6 +236,20 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) store_c<T, VEC>(a, c, Hc, s * 16, g, colbase + nt * 16 + nl, acc[nt]);
   }
+}
+
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
+__global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, blockIdx.x, blockIdx.y);
+}
+
+// Batched form: matrix blockIdx.z of the table (single-chunk panels); strips past
+// that matrix's columns return at once (before any barrier).
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
+__global__ void __launch_bounds__(NW * 64) k_larfb_reg_b(const LarfbArgs<T>* __restrict__ tab) {
+  const LarfbArgs<T>& a = tab[blockIdx.z];
+  if (a.col0 + (int64_t)blockIdx.x * IB * 16 >= a.col1 || a.k <= 0) return;
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, blockIdx.x, 0);
 }
 
 // Streaming variant, for strips that do not fit in registers: C is read in
@@ -487,6 +500,83 @@ static hipError_t launch_larfb_kt(int nw, int ib, const LarfbArgs<T>& a, hipStre
   return hipErrorInvalidConfiguration;
 }
 
+template <typename T, int KT, int IB, int NW, bool VEC, int PREC>
+static hipError_t launch_larfb_reg_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, hipStream_t st) {
+  constexpr int SPW = larfb_spw(KT * 16, NW);
+  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg_b<T, KT, IB, NW, SPW, VEC, PREC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  const dim3 grid((unsigned)((max_ncols + IB * 16 - 1) / (IB * 16)), 1, (unsigned)count);
+  hipLaunchKernelGGL((k_larfb_reg_b<T, KT, IB, NW, SPW, VEC, PREC>), grid, dim3(NW * 64), lds, st, tab);
+  return hipGetLastError();
+}
+
+template <typename T, int KT, int IB, int NW>
+static hipError_t launch_larfb_b_nw(int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t max_ncols,
+                                    hipStream_t st) {
+  if constexpr (larfb_reg_valid<T>(KT, IB, NW)) {
+    if constexpr (sizeof(T) == 4) {
+      switch (prec * 2 + (vec ? 1 : 0)) {
+        case 0: return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, st);
+        case 1: return launch_larfb_reg_b<T, KT, IB, NW, true, 0>(tab, count, max_ncols, st);
+        case 4: return launch_larfb_reg_b<T, KT, IB, NW, false, 2>(tab, count, max_ncols, st);
+        case 5: return launch_larfb_reg_b<T, KT, IB, NW, true, 2>(tab, count, max_ncols, st);
+        case 6: return launch_larfb_reg_b<T, KT, IB, NW, false, 3>(tab, count, max_ncols, st);
+        case 7: return launch_larfb_reg_b<T, KT, IB, NW, true, 3>(tab, count, max_ncols, st);
+      }
+      return hipErrorInvalidValue;
+    } else {
+      if (prec != 0) return hipErrorInvalidValue;
+      return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, st);
+    }
+  } else {
+    return hipErrorInvalidConfiguration;  // the batched path needs the register-strip form
+  }
+}
+
+template <typename T, int KT, int IB>
+static hipError_t launch_larfb_b_ib(int nw, int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t mc,
+                                    hipStream_t st) {
+  switch (nw) {
+    case 1: return launch_larfb_b_nw<T, KT, IB, 1>(prec, vec, tab, count, mc, st);
+    case 2: return launch_larfb_b_nw<T, KT, IB, 2>(prec, vec, tab, count, mc, st);
+    case 4: return launch_larfb_b_nw<T, KT, IB, 4>(prec, vec, tab, count, mc, st);
+    case 8: return launch_larfb_b_nw<T, KT, IB, 8>(prec, vec, tab, count, mc, st);
+    case 16: return launch_larfb_b_nw<T, KT, IB, 16>(prec, vec, tab, count, mc, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T, int KT>
+static hipError_t launch_larfb_b_kt(int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t mc,
+                                    hipStream_t st) {
+  switch (ib) {
+    case 1: return launch_larfb_b_ib<T, KT, 1>(nw, prec, vec, tab, count, mc, st);
+    case 2: return launch_larfb_b_ib<T, KT, 2>(nw, prec, vec, tab, count, mc, st);
+    case 4: return launch_larfb_b_ib<T, KT, 4>(nw, prec, vec, tab, count, mc, st);
+    case 8: return launch_larfb_b_ib<T, KT, 8>(nw, prec, vec, tab, count, mc, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T>
+hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,
+                                int64_t max_ncols, hipStream_t st) {
+  if (count <= 0 || max_ncols <= 0) return hipSuccess;
+  switch (tile) {
+    case 16: return launch_larfb_b_kt<T, 1>(nw, ib, prec, vec, tab, count, max_ncols, st);
+    case 32: return launch_larfb_b_kt<T, 2>(nw, ib, prec, vec, tab, count, max_ncols, st);
+    case 64: return launch_larfb_b_kt<T, 4>(nw, ib, prec, vec, tab, count, max_ncols, st);
+    case 128: return launch_larfb_b_kt<T, 8>(nw, ib, prec, vec, tab, count, max_ncols, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
   if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
@@ -501,5 +591,9 @@ hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStre
 
 template hipError_t launch_larfb<float>(int, int, int, const LarfbArgs<float>&, hipStream_t);
 template hipError_t launch_larfb<double>(int, int, int, const LarfbArgs<double>&, hipStream_t);
+template hipError_t launch_larfb_batched<float>(int, int, int, int, int, const LarfbArgs<float>*, int, int64_t,
+                                                hipStream_t);
+template hipError_t launch_larfb_batched<double>(int, int, int, int, int, const LarfbArgs<double>*, int, int64_t,
+                                                 hipStream_t);
 
 }  // namespace svdv
