@@ -183,6 +183,35 @@ int svdv_last_timing(double* ms, int n);
  */
 int svdv_last_kernel_stats(int kind, double* out, int n);
 
+/*
+ * Learned cost model of the auto-tuner (GPU kernels; the paper's tuning loop,
+ * Eq. 1, chooses x* = argmin f(K_x) over measured times -- this model predicts
+ * f from a configuration's features so that only the most promising
+ * configurations need measuring).
+ * A 3-layer perceptron SVDV_MLP_IN -> SVDV_MLP_HIDDEN -> SVDV_MLP_HIDDEN -> 1
+ * with ReLU, float32.  params: device vector of SVDV_MLP_NPARAM floats laid out
+ * as W1[IN][H] (row-major), b1[H], W2[H][H], b2[H], w3[H], b3.  X: device,
+ * n x IN row-major features; t, y: device, n floats.
+ *   svdv_mlp_forward   y = model(X).
+ *   svdv_mlp_gradient  grad (device, NPARAM floats) = d loss / d params with
+ *                      loss = (1/n) sum (model(X) - t)^2, written to *loss
+ *                      (device float) when loss is not NULL; work: device
+ *                      scratch of svdv_mlp_work_size(n) floats owned by the caller.
+ *   svdv_mlp_adam_step one Adam update (step >= 1) of params with moment
+ *                      vectors m, v (device, NPARAM floats each, zero at step 1).
+ * All run on `stream`, return SVDV_OK or an error status.
+ */
+#define SVDV_MLP_IN 6
+#define SVDV_MLP_HIDDEN 64
+#define SVDV_MLP_NPARAM (SVDV_MLP_IN * SVDV_MLP_HIDDEN + SVDV_MLP_HIDDEN + SVDV_MLP_HIDDEN * SVDV_MLP_HIDDEN + \
+                         SVDV_MLP_HIDDEN + SVDV_MLP_HIDDEN + 1)
+int64_t svdv_mlp_work_size(int64_t n);
+int svdv_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream);
+int svdv_mlp_gradient(const float* params, const float* X, const float* t, int64_t n, float* grad, float* loss,
+                      float* work, void* stream);
+int svdv_mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                       float beta2, float eps, void* stream);
+
 /* Text for a status code (static string). */
 const char* svdv_status_string(int status);
 /* Detail of the last error on the calling thread (thread-local, static lifetime). */

@@ -23,7 +23,8 @@ STATUS = {0: "SVDV_OK", -1: "SVDV_ERR_INVALID_ARG", -2: "SVDV_ERR_UNSUPPORTED", 
 EXPORTS = ["svd_values", "svd_values_ex", "svd_values_batched", "svdv_default_config", "svdv_check_config",
            "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
            "svdv_last_error", "svdv_release", "svdv_timing", "svdv_last_timing",
-           "svdv_last_kernel_stats"]
+           "svdv_last_kernel_stats", "svdv_mlp_work_size", "svdv_mlp_forward", "svdv_mlp_gradient",
+           "svdv_mlp_adam_step"]
 
 
 class SvdvError(RuntimeError):
@@ -82,11 +83,17 @@ def lib():
             "svdv_timing": [ctypes.c_int],
             "svdv_last_timing": [ctypes.POINTER(ctypes.c_double), ctypes.c_int],
             "svdv_last_kernel_stats": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+            "svdv_mlp_forward": [vp, vp, i64, vp, vp],
+            "svdv_mlp_gradient": [vp, vp, vp, i64, vp, vp, vp, vp],
+            "svdv_mlp_adam_step": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.svdv_mlp_work_size.argtypes = [i64]
+        L.svdv_mlp_work_size.restype = i64
         L.svdv_status_string.argtypes = [ctypes.c_int]
         L.svdv_status_string.restype = ctypes.c_char_p
         L.svdv_last_error.argtypes = []
@@ -289,3 +296,39 @@ def last_kernel_stats(kind: str) -> dict:
 
 def release():
     _check(lib().svdv_release())
+
+
+# --------------------------------------------------------------------------- learned cost model kernels
+
+MLP_IN, MLP_HIDDEN = 6, 64
+MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_forward(params, X, out=None):
+    """Model outputs for the rows of X (float32 CUDA tensors; params has MLP_NPARAM entries)."""
+    torch = _torch()
+    y = out if out is not None else torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().svdv_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), _stream(X.device)))
+    return y
+
+
+def mlp_work(n: int, device):
+    torch = _torch()
+    return torch.empty(max(1, int(lib().svdv_mlp_work_size(n))), dtype=torch.float32, device=device)
+
+
+def mlp_gradient(params, X, t, grad, loss=None, work=None):
+    """grad <- d/dparams of mean((model(X) - t)^2); loss (1-element tensor) receives the loss."""
+    work = work if work is not None else mlp_work(X.shape[0], X.device)
+    _check(lib().svdv_mlp_gradient(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grad),
+                                   _ptr(loss) if loss is not None else None, _ptr(work), _stream(X.device)))
+    return grad
+
+
+def mlp_adam_step(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().svdv_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                                    _stream(params.device)))

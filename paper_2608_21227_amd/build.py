@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsvdv.so")
-SOURCES = ["stage1.hip", "update.hip", "stage2.hip", "stage3.hip", "svdv.cpp"]
+SOURCES = ["stage1.hip", "update.hip", "stage2.hip", "stage3.hip", "mlp.hip", "svdv.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 # Packed FP32 instructions are switched off for all device code (they are not

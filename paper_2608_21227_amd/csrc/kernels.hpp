@@ -7,6 +7,9 @@
 
 namespace svdv {
 
+// Records an error detail for svdv_last_error and returns status.
+int report_error(int status, const char* msg);
+
 // Rows per lane of the chunk-QR kernel (16 waves, one chunk in registers):
 // 64 * RPT rows * TILE columns = 32 elements per thread (16 for float64 at
 // tile 16, whose single column per wave would otherwise not fit in registers).

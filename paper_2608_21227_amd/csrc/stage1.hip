@@ -22,6 +22,22 @@
 
 namespace svdv {
 
+// Optional phase trace of the panel kernel (diagnostic builds only, -DSVDV_PANEL_TRACE):
+// for each of the first 4096 launches of workgroup 0, five timestamps of the 100 MHz counter.
+#ifdef SVDV_PANEL_TRACE
+__device__ uint64_t g_panel_trace[5 * 4096];
+__device__ int g_panel_calls;
+#define PANEL_MARK(slot, k)                                                        \
+  do {                                                                             \
+    if (threadIdx.x == 0 && (slot) >= 0 && (slot) < 4096)                          \
+      g_panel_trace[(slot) * 5 + (k)] = __builtin_amdgcn_s_memrealtime();          \
+  } while (0)
+#else
+#define PANEL_MARK(slot, k) \
+  do {                      \
+  } while (0)
+#endif
+
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -136,6 +152,15 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
 
   T x[RPT][CPT];
 
+#ifdef SVDV_PANEL_TRACE
+  __shared__ int s_slot;
+  if (threadIdx.x == 0) s_slot = (blockIdx.x == 0 && c == 0) ? atomicAdd(&g_panel_calls, 1) : -1;
+  __syncthreads();
+  const int slot = s_slot;
+#else
+  const int slot = -1;
+#endif
+  PANEL_MARK(slot, 0);
   // ---- load the chunk, with the global loads issued in bursts ----
   // rows contiguous (QR sweep): lane l reads rows i*64+l of its columns directly
   // (coalesced along rows).  Otherwise (LQ sweep) threads read along the
@@ -183,6 +208,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
     }
   }
 
+  PANEL_MARK(slot, 1);
   // ---- Householder loop over the panel columns ----
   for (int j = 0; j < kr; ++j) {
     const int ow = j / CPT, oc = j % CPT;
@@ -257,6 +283,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   }
   __syncthreads();
 
+  PANEL_MARK(slot, 2);
   // ---- compact-WY factor: T = inverse of (diag(1/tau) + strict upper of V^T V), by doubling ----
   for (int bs = 1; bs < kr; bs *= 2) {
     const int npair = (kr + 2 * bs - 1) / (2 * bs);
@@ -284,6 +311,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
     __syncthreads();
   }
 
+  PANEL_MARK(slot, 3);
   // ---- outputs: T (TILE x TILE, column-major, zero outside kr), V, R ----
   T* Tout = a.Tm + (int64_t)c * TILE * TILE;
   for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
@@ -313,6 +341,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
       if (q < kr && q <= gc) a.M.at(a.rm.row(c, q), a.pc + gc) = x[i][cc];
     }
   }
+  PANEL_MARK(slot, 4);
 }
 
 template <typename T, int TILE, int RPT>
@@ -553,3 +582,9 @@ SVDV_INST(float)
 SVDV_INST(double)
 
 }  // namespace svdv
+
+#ifdef SVDV_PANEL_TRACE
+extern "C" int svdv_panel_trace(uint64_t* out, int count) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(svdv::g_panel_trace), (size_t)count * 8);
+}
+#endif

@@ -794,6 +794,11 @@ int batched_run(BatchPlan& P, const void* const* A_array, void* S, hipStream_t s
 
 }  // namespace
 
+namespace svdv {
+// Records an error detail for svdv_last_error (used by the other source files).
+int report_error(int status, const char* msg) { return fail(status, msg); }
+}  // namespace svdv
+
 // ============================================================================
 // C ABI
 // ============================================================================

@@ -238,18 +238,34 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear workgroup id, and
+// each XCD has its own L2.  Neighbouring strips share 128-byte lines when the
+// strip runs along memory rows (LQ sweep: 16 floats = half a line), so the
+// linear ids are permuted to put strips 2j and 2j+1 on workgroups id and id + 8
+// (same XCD): the second half of each line is then an L2 hit, not a second HBM
+// read.  Groups of 16 ids are permuted; a ragged tail keeps its ids.
+__device__ __forceinline__ int64_t xcd_pair_id(int64_t id, int64_t count) {
+  const int64_t full = count / 16 * 16;
+  if (id >= full) return id;
+  const int64_t g = id / 16, r = id % 16;
+  return g * 16 + (r % 8) * 2 + r / 8;
+}
+
 template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
 __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
-  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, blockIdx.x, blockIdx.y);
+  const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.y * gridDim.x, (int64_t)gridDim.x * gridDim.y);
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, (int)(id % gridDim.x), (int)(id / gridDim.x));
 }
 
 // Batched form: matrix blockIdx.z of the table (single-chunk panels); strips past
 // that matrix's columns return at once (before any barrier).
 template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
 __global__ void __launch_bounds__(NW * 64) k_larfb_reg_b(const LarfbArgs<T>* __restrict__ tab) {
-  const LarfbArgs<T>& a = tab[blockIdx.z];
-  if (a.col0 + (int64_t)blockIdx.x * IB * 16 >= a.col1 || a.k <= 0) return;
-  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, blockIdx.x, 0);
+  const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.z * gridDim.x, (int64_t)gridDim.x * gridDim.z);
+  const int strip = (int)(id % gridDim.x);
+  const LarfbArgs<T>& a = tab[id / gridDim.x];
+  if (a.col0 + (int64_t)strip * IB * 16 >= a.col1 || a.k <= 0) return;
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, strip, 0);
 }
 
 // Streaming variant, for strips that do not fit in registers: C is read in
