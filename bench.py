@@ -213,7 +213,7 @@ def main():
     es = 4 if dtype == "float32" else 8
     ridge = (PEAKS["fp32_TF"] if dtype == "float32" else PEAKS["fp64_TF"]) * 1e12 / (PEAKS["hbm_GBs"] * 1e9)
     kinds = {}
-    t_chase = stages.get("chase", float("nan")) * 1e-3
+    t_chase = stages.get("chase_kernel", stages.get("chase", float("nan"))) * 1e-3
     fl = chase_flops(n, b)
     kinds["chase"] = {"kernel": "k_chase_* (stage 2 bulge chase, float64; one launch per call)", "launches": 1,
                       "ms": t_chase * 1e3, "bound": "alu", "achieved": fl / t_chase / 1e12,

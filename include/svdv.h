@@ -164,7 +164,8 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* 
  * [1] stage 1 (all panel and update launches), [2] band packing, [3] the
  * bulge-chase kernel, [4] the bisection kernels.  svdv_last_timing waits for
  * the last call's events and writes up to n elapsed times in milliseconds
- * (HOST array) followed by [5] the whole call; returns the count written.
+ * (HOST array) followed by [5] the whole call and [6] the bulge-chase launch
+ * alone; returns the count written.
  * svdv_timing(2) in addition brackets every stage-1 kernel launch with an event
  * pair (for svdv_last_kernel_stats; the extra events lengthen stage 1);
  * svdv_timing(0) switches timing off.

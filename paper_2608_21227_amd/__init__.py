@@ -268,7 +268,7 @@ def apply_qt(V, T, C, side: int = 0, config=None):
     return C
 
 
-STAGES = ["stage_in", "stage1", "band_pack", "chase", "bisect", "total"]
+STAGES = ["stage_in", "stage1", "band_pack", "chase", "bisect", "total", "chase_kernel"]
 
 
 def set_timing(enable, kernels: bool = False):
@@ -279,8 +279,8 @@ def set_timing(enable, kernels: bool = False):
 
 def last_timing() -> dict:
     """Per-stage milliseconds of the last timed call (waits for its events)."""
-    buf = (ctypes.c_double * 6)()
-    k = lib().svdv_last_timing(buf, 6)
+    buf = (ctypes.c_double * 7)()
+    k = lib().svdv_last_timing(buf, 7)
     if k < 0:
         _check(k)
     return {name: buf[i] for i, name in enumerate(STAGES[:k])}

@@ -164,9 +164,11 @@ hipError_t launch_chase_batched(const ChaseArgs& L, int grid, int count, int64_t
                                 int64_t zero_count, hipStream_t st);
 
 // Stage 3.
+// fail_flag (optional): when it holds a nonzero value (a bounded wait of the chase
+// gave up), every output value is NaN.
 template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in,
-                         int lanes_per_value, hipStream_t st);
+                         int lanes_per_value, hipStream_t st, const int* fail_flag = nullptr);
 // Batched: value v (0 <= v < total) of the flattened batch is value v - voff[vmat[v]] of matrix vmat[v].
 template <typename T>
 hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,

@@ -111,10 +111,15 @@ __device__ __forceinline__ void bisect_team(const double* __restrict__ work, int
 }
 
 template <typename T>
-__global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S, const int* exp_in, int lps) {
+__global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S, const int* exp_in, int lps,
+                         const int* fail_flag) {
   const int lane = threadIdx.x & 63;
   const int teams_per_wave = 64 / lps;
   const int64_t k = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
+  if (fail_flag != nullptr && *fail_flag != 0) {  // the bidiagonal is not valid: fail loudly
+    if (k < n && lane % lps == 0) S[n - 1 - k] = (T)__builtin_nan("");
+    return;
+  }
   bisect_team(work, n, S, exp_in, k, k < n, lps);
 }
 
@@ -134,12 +139,12 @@ __global__ void k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __res
 
 template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in, int lps,
-                         hipStream_t st) {
+                         hipStream_t st, const int* fail_flag) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bisect_prep, dim3(1), dim3(256), 0, st, d, e, n, work);
   const int teams_per_block = 256 / lps;
   const int64_t blocks = (n + teams_per_block - 1) / teams_per_block;
-  hipLaunchKernelGGL(k_bisect<T>, dim3((unsigned)blocks), dim3(256), 0, st, work, n, S, exp_in, lps);
+  hipLaunchKernelGGL(k_bisect<T>, dim3((unsigned)blocks), dim3(256), 0, st, work, n, S, exp_in, lps, fail_flag);
   return hipGetLastError();
 }
 
@@ -158,8 +163,8 @@ template hipError_t launch_bisect_batched<float>(const BatchMat<float>*, int, co
 template hipError_t launch_bisect_batched<double>(const BatchMat<double>*, int, const int*, const int64_t*, int64_t,
                                                   int, hipStream_t);
 template hipError_t launch_bisect<float>(const double*, const double*, int64_t, float*, double*, const int*, int,
-                                         hipStream_t);
+                                         hipStream_t, const int*);
 template hipError_t launch_bisect<double>(const double*, const double*, int64_t, double*, double*, const int*, int,
-                                          hipStream_t);
+                                          hipStream_t, const int*);
 
 }  // namespace svdv

@@ -48,11 +48,17 @@ struct Timing {
   bool kernels = false;  // also bracket every stage-1 launch (svdv_timing(2))
   bool valid = false;
   hipEvent_t ev[7] = {};
+  hipEvent_t cev[2] = {};  // around the bulge-chase launch, on the stream it runs on
   KernelLog klog[2];
   void mark(int i, hipStream_t st) {
     if (!enabled) return;
     if (!ev[i]) hipEventCreate(&ev[i]);
     hipEventRecord(ev[i], st);
+  }
+  void chase_mark(int i, hipStream_t st) {
+    if (!enabled) return;
+    if (!cev[i]) hipEventCreate(&cev[i]);
+    hipEventRecord(cev[i], st);
   }
   void begin_call() {
     valid = false;
@@ -428,7 +434,7 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   }
   HIPCHK(launch_band_pack<T>(W, ldw, N, cfg.tile, Bs, 3 * cfg.tile, expo, 0, st));
   g_timing.mark(3, st);
-  ChaseArgs ca;
+  ChaseArgs ca{};
   ca.Bs = Bs;
   ca.ldb = 3 * cfg.tile;
   ca.n = N;
@@ -442,9 +448,11 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   int grid = chase_grid(ca.ngroups, cfg.tile, cfg.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
+  g_timing.chase_mark(0, st);
   HIPCHK(launch_chase(ca, grid, st));
+  g_timing.chase_mark(1, st);
   g_timing.mark(4, st);
-  if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 16, st));
+  if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 16, st, err));
   g_timing.mark(5, st);
   g_timing.valid = g_timing.enabled;
   return SVDV_OK;
@@ -886,7 +894,7 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   if (rc) return rc;
   double* Bs = (double*)(ws + L.Bs);
   HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
-  ChaseArgs ca;
+  ChaseArgs ca{};
   ca.Bs = Bs;
   ca.ldb = 3 * b;
   ca.n = n;
@@ -1054,6 +1062,11 @@ int svdv_last_timing(double* ms, int n) {
     HIPCHK(hipEventElapsedTime(&t, g_timing.ev[0], g_timing.ev[5]));
     ms[k++] = t;
   }
+  if (k < n) {  // the bulge-chase launch itself, on its own stream
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, g_timing.cev[0], g_timing.cev[1]));
+    ms[k++] = t;
+  }
   return k;
 }
 
@@ -1114,7 +1127,7 @@ extern "C" int svdv_debug_chase(const double* band, int64_t n, int64_t b, int64_
   if (rc) return rc;
   double* Bs = (double*)(ws + L.Bs);
   HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
-  ChaseArgs ca;
+  ChaseArgs ca{};
   ca.Bs = Bs;
   ca.ldb = 3 * b;
   ca.n = n;
