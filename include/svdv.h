@@ -137,7 +137,10 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
 
 /*
  * svdv_stage_values: stage 3.  Singular values of the upper bidiagonal (d, e)
- * (float64, n and n-1 entries), written descending to S in out_dtype.
+ * (float64, n and n-1 entries), written descending to S in out_dtype.  Each
+ * value is located by Sturm-count multisection in float64 to an absolute
+ * width of 4u (max|d| + max|e|) for SVDV_F64 output and 2^-32 (max|d| + max|e|)
+ * for SVDV_F32 output, then rounded to out_dtype.
  */
 int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_dtype, void* S, void* stream);
 

@@ -99,7 +99,7 @@ struct BatchMat {
   double* Bs;            // chase storage (N x 3b)
   double* d;
   double* e;
-  double* work;          // bisection work (2N + 2)
+  double* work;          // bisection work (bisect_work_doubles(N))
   T* S;                  // output singular values (min(m, n))
 };
 
@@ -164,14 +164,24 @@ hipError_t launch_chase_batched(const ChaseArgs& L, int grid, int count, int64_t
                                 int64_t zero_count, hipStream_t st);
 
 // Stage 3.
+// Work array of an n x n bidiagonal: d_i^2 [n], e_i^2 [n], bound, pivmin, then
+// the int32 counts of the shared grid (bisect_grid_points(n) of them).
+__host__ __device__ inline int64_t bisect_grid_points(int64_t n) { return 16 * n; }
+__host__ __device__ inline int64_t bisect_work_doubles(int64_t n) { return 2 * n + 2 + (bisect_grid_points(n) + 1) / 2; }
+__host__ __device__ inline int* bisect_grid_counts(double* work, int64_t n) { return (int*)(work + 2 * n + 2); }
+__host__ __device__ inline const int* bisect_grid_counts(const double* work, int64_t n) {
+  return (const int*)(work + 2 * n + 2);
+}
+// lanes_per_value: 8, 16, 32 or 64, or 0 to choose from n.
 // fail_flag (optional): when it holds a nonzero value (a bounded wait of the chase
 // gave up), every output value is NaN.
 template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in,
                          int lanes_per_value, hipStream_t st, const int* fail_flag = nullptr);
-// Batched: value v (0 <= v < total) of the flattened batch is value v - voff[vmat[v]] of matrix vmat[v].
+// Batched: value v (0 <= v < total) of the flattened batch is value v - voff[vmat[v]] of matrix vmat[v];
+// max_n is the largest N of the batch.
 template <typename T>
 hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
-                                 int lps, hipStream_t st);
+                                 int64_t max_n, hipStream_t st);
 
 }  // namespace svdv

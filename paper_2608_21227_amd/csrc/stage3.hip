@@ -4,11 +4,14 @@
 // negative pivots of the LDL^T factorisation of B^T B - x^2 I, obtained from
 // B's entries by the stationary qd recurrence
 //     s_1 = -x^2;  D+_i = d_i^2 + s_i;  s_{i+1} = e_i^2 s_i / D+_i - x^2,
-// (a pivot smaller than pivmin in magnitude is replaced by -pivmin).
-// Each singular value is located by multisection: a team of LPS lanes
-// evaluates the count at LPS interior points of the current interval, which
-// shrinks it by a factor LPS+1 per round, until it is narrower than 4u times
-// the bound max|d| + max|e| on sigma_max.
+// (a pivot smaller than pivmin in magnitude is replaced by -pivmin; pivmin is a
+// power of two far below the rounding error, chosen so that no pivot or
+// reciprocal leaves the normal range).
+// Counts on a shared grid of 16 n points give every singular value a starting
+// cell; a team of LPS lanes then multisects it: LPS interior points of the
+// current interval per round, which shrink it by a factor LPS+1, until it is
+// narrower than the tolerance (4u times the bound max|d| + max|e| on
+// sigma_max for float64 output, 2^-32 times it for float32 output).
 #include "common.hpp"
 #include "kernels.hpp"
 #include <float.h>
@@ -39,8 +42,13 @@ __device__ __forceinline__ void bisect_prep_body(const double* __restrict__ d, c
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    work[2 * n] = (smax[0][0] + smax[1][0]) * (1.0 + 1e-14) + DBL_MIN;
-    work[2 * n + 1] = DBL_MIN * fmax(1.0, smax[2][0]);
+    const double bound = (smax[0][0] + smax[1][0]) * (1.0 + 1e-14) + DBL_MIN;
+    work[2 * n] = bound;
+    // pivmin = 2^p >= bound^2 2^-896.  With G = bound^2 >= d_i^2, e_i^2, x^2 every
+    // |s_i| <= 2 G^2 / pivmin + G <= 2^897 G and every |D+_i| >= pivmin, so all
+    // pivots and their reciprocals stay normal (as long as G < 2^120).  Pivots this
+    // small are a perturbation far below the rounding error of the reduction.
+    work[2 * n + 1] = ldexp(1.0, max(2 * ilogb(bound) + 2 - 896, -1000));
   }
 }
 
@@ -53,52 +61,146 @@ __global__ void k_bisect_prep_b(const BatchMat<T>* __restrict__ tab) {
   bisect_prep_body(t.d, t.e, t.N, t.work);
 }
 
+// Quotient a / b by a reciprocal and Newton-Raphson (Markstein's scheme): the
+// hardware reciprocal r ~ 1/b (about 24 correct bits) is refined once,
+// r += r (1 - b r), then q = a r gets one residual correction q += r (a - b q).
+// Valid for normal b whose reciprocal is normal, which the choice of pivmin
+// guarantees for every pivot; the result is within one unit in the last place
+// of the rounded quotient.
+__device__ __forceinline__ double nr_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
+// Sturm count of one shift x: the number of negative pivots.  d_i^2 and e_i^2 are
+// fetched 8 steps at a time (wave-uniform addresses, so scalar loads that are in
+// flight while the previous 8 steps run).  pivmin is a power of two, so
+// |D+| < pivmin is decided exactly on the high 32 bits of D+; the sign bit of
+// the (possibly replaced) pivot is the count.
 __device__ __forceinline__ int sturm_count(const double* __restrict__ dd, const double* __restrict__ ee, int64_t n,
                                            double x, double pivmin) {
   const double t = x * x;
+  const uint32_t piv_hi = (uint32_t)(__double_as_longlong(pivmin) >> 32);
+  const double negpiv = -pivmin;
   double s = -t;
   int cnt = 0;
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    double dp = dd[i] + s;
-    if (fabs(dp) < pivmin) dp = -pivmin;
-    cnt += dp < 0.0;
-    s = ee[i] * (s / dp) - t;
+  auto pivot = [&](double di) {
+    double dp = di + s;
+    const uint32_t hi = (uint32_t)(__double_as_longlong(dp) >> 32);
+    const bool tiny = (hi & 0x7fffffffu) < piv_hi;
+    dp = tiny ? negpiv : dp;
+    cnt += tiny ? 1 : (int)(hi >> 31);
+    return dp;
+  };
+  int64_t i = 0;
+  for (; i + 8 < n; i += 8) {
+    double dv[8], ev[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dv[u] = dd[i + u];
+      ev[u] = ee[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = fma(ev[u], nr_div(s, pivot(dv[u])), -t);
   }
-  double dp = dd[n - 1] + s;
-  if (fabs(dp) < pivmin) dp = -pivmin;
-  cnt += dp < 0.0;
+  for (; i + 1 < n; ++i) s = fma(ee[i], nr_div(s, pivot(dd[i])), -t);
+  pivot(dd[n - 1]);  // last pivot (no e beyond it)
   return cnt;
+}
+
+// Shared count grid: counts at G = 16 n points x_g = bound (g + 1) / (G + 1),
+// evaluated once for all values (one lane per point).  Every value's search then
+// starts from the grid cell that holds it instead of from [0, bound], which
+// saves the first rounds of multisection that all values would repeat.
+__device__ __forceinline__ double grid_x(double bound, int64_t g, int64_t G) {
+  return bound * (double)(g + 1) / (double)(G + 1);
+}
+
+__device__ __forceinline__ void bisect_grid_body(const double* __restrict__ work, int64_t n, int64_t g0) {
+  const int64_t G = bisect_grid_points(n);
+  const int64_t g = g0 + threadIdx.x;
+  const double bound = work[2 * n], pivmin = work[2 * n + 1];
+  const int c = sturm_count(work, work + n, n, grid_x(bound, g < G ? g : G - 1, G), pivmin);
+  if (g < G) bisect_grid_counts(const_cast<double*>(work), n)[g] = c;
+}
+
+__global__ void __launch_bounds__(256) k_bisect_grid(const double* __restrict__ work, int64_t n) {
+  bisect_grid_body(work, n, (int64_t)blockIdx.x * blockDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bisect_grid_b(const BatchMat<T>* __restrict__ tab) {
+  const BatchMat<T>& t = tab[blockIdx.y];
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+  if (g0 >= bisect_grid_points(t.N)) return;  // whole workgroup leaves together
+  bisect_grid_body(t.work, t.N, g0);
 }
 
 // One team of lps lanes locates value k (k-th smallest) of the bidiagonal whose
 // prepared work array is `work`; inactive teams (active = false) still take part
 // in the wave-wide votes.
+//  1. Grid search: an lps-ary search over the grid counts finds the cell
+//     (x_{g-1}, x_g] with count(x_{g-1}) <= k < count(x_g) (x_{-1} = 0, x_G = bound).
+//  2. Multisection: each round the team's lanes evaluate lps interior points of
+//     the interval, which shrinks it (lps + 1)-fold, until it is narrower than
+//     tol: 4u bound for float64 output, 2^-32 bound for float32 output (far
+//     below float32's rounding of any value above 2^-8 sigma_max, and below the
+//     float32 reduction's own error for every value).
 template <typename T>
 __device__ __forceinline__ void bisect_team(const double* __restrict__ work, int64_t n, T* __restrict__ S,
                                             const int* exp_in, int64_t k, bool active, int lps) {
   const double* dd = work;
   const double* ee = work + n;
+  const int* gc = bisect_grid_counts(work, n);
+  const int64_t G = bisect_grid_points(n);
   const double bound = active ? work[2 * n] : 0.0;
   const double pivmin = active ? work[2 * n + 1] : 0.0;
   const int lane = threadIdx.x & 63;
   const int team_in_wave = lane / lps, j = lane % lps;
-  double lo = 0.0, hi = bound;
-  const double tol = 4.0 * DBL_EPSILON * bound;
-  const uint64_t team_mask = (lps == 64) ? ~0ull : (((1ull << lps) - 1) << (team_in_wave * lps));
+  const int team_base = team_in_wave * lps;
+  const uint64_t team_mask = (lps == 64) ? ~0ull : (((1ull << lps) - 1) << team_base);
+
+  // 1. grid search, invariant count(lo_i) <= k < count(hi_i)
+  int64_t lo_i = -1, hi_i = G;
+  while (__any(active && hi_i - lo_i > 1)) {
+    const int64_t m = hi_i - lo_i - 1;  // interior indices lo_i+1 .. hi_i-1
+    const bool live = active && m > 0;
+    const int64_t pj = lo_i + 1 + (j * m) / lps;
+    const bool above = live && gc[pj] > k;
+    const uint64_t ball = __ballot(above) & team_mask;
+    if (live) {
+      if (ball == 0) {
+        lo_i = lo_i + 1 + ((int64_t)(lps - 1) * m) / lps;
+      } else {
+        const int f = __builtin_ctzll(ball) - team_base;
+        hi_i = lo_i + 1 + ((int64_t)f * m) / lps;
+        if (f > 0) lo_i = lo_i + 1 + ((int64_t)(f - 1) * m) / lps;
+      }
+    }
+  }
+  double lo = lo_i < 0 ? 0.0 : grid_x(bound, lo_i, G);
+  double hi = hi_i >= G ? bound : grid_x(bound, hi_i, G);
+
+  // 2. multisection
+  const double npts = (double)(lps + 1);
+  const double tol = sizeof(T) == 4 ? ldexp(bound, -32) : 4.0 * DBL_EPSILON * bound;
   for (int it = 0; it < 80; ++it) {
     // every lane of the wave runs the same number of rounds (wave-uniform control)
     const bool need = active && (hi - lo > tol);
     if (!__any(need)) break;
-    const double x = lo + (hi - lo) * (double)(j + 1) / (double)(lps + 1);
-    const int cnt = active ? sturm_count(dd, ee, n, x, pivmin) : 0;
-    const uint64_t ball = __ballot(cnt > k) & team_mask;
+    const double x = lo + (hi - lo) * (double)(j + 1) / npts;
+    const bool above = active && sturm_count(dd, ee, n, x, pivmin) > k;
+    // first point (in x order) whose count exceeds k (counts increase with x)
+    const uint64_t ball = __ballot(above) & team_mask;
     if (need) {
       if (ball == 0) {
-        lo = lo + (hi - lo) * (double)lps / (double)(lps + 1);
+        lo = lo + (hi - lo) * (npts - 1.0) / npts;
       } else {
-        const int first = __builtin_ctzll(ball) - team_in_wave * lps;  // smallest point with count > k
-        const double nhi = lo + (hi - lo) * (double)(first + 1) / (double)(lps + 1);
-        const double nlo = first == 0 ? lo : lo + (hi - lo) * (double)first / (double)(lps + 1);
+        const int first = __builtin_ctzll(ball) - team_base;
+        const double nhi = lo + (hi - lo) * (double)(first + 1) / npts;
+        const double nlo = first == 0 ? lo : lo + (hi - lo) * (double)first / npts;
         lo = nlo;
         hi = nhi;
       }
@@ -111,8 +213,8 @@ __device__ __forceinline__ void bisect_team(const double* __restrict__ work, int
 }
 
 template <typename T>
-__global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S, const int* exp_in, int lps,
-                         const int* fail_flag) {
+__global__ void __launch_bounds__(256) k_bisect(const double* __restrict__ work, int64_t n, T* __restrict__ S,
+                                                const int* exp_in, int lps, const int* fail_flag) {
   const int lane = threadIdx.x & 63;
   const int teams_per_wave = 64 / lps;
   const int64_t k = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
@@ -126,8 +228,8 @@ __global__ void k_bisect(const double* __restrict__ work, int64_t n, T* __restri
 // Batched form: value v of the flattened batch belongs to matrix vmat[v] as its
 // value v - voff[vmat[v]].
 template <typename T>
-__global__ void k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __restrict__ vmat,
-                           const int64_t* __restrict__ voff, int64_t total, int lps) {
+__global__ void __launch_bounds__(256) k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __restrict__ vmat,
+                                                  const int64_t* __restrict__ voff, int64_t total, int lps) {
   const int lane = threadIdx.x & 63;
   const int teams_per_wave = 64 / lps;
   const int64_t v = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
@@ -137,11 +239,23 @@ __global__ void k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __res
   bisect_team(t.work, t.N, t.S, t.exp, active ? v - voff[mi] : 0, active, lps);
 }
 
+// Lanes per value: about 64K lanes in all (one wave per SIMD) when there are
+// enough values, at most 64 (one wave) per value.
+static int bisect_lps(int64_t values) {
+  int lps = 8;
+  while (lps < 64 && (int64_t)lps * values < 65536) lps *= 2;
+  return lps;
+}
+
 template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in, int lps,
                          hipStream_t st, const int* fail_flag) {
   if (n <= 0) return hipSuccess;
+  if (lps <= 0) lps = bisect_lps(n);
+  if (lps != 8 && lps != 16 && lps != 32 && lps != 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_bisect_prep, dim3(1), dim3(256), 0, st, d, e, n, work);
+  const int64_t G = bisect_grid_points(n);
+  hipLaunchKernelGGL(k_bisect_grid, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st, work, n);
   const int teams_per_block = 256 / lps;
   const int64_t blocks = (n + teams_per_block - 1) / teams_per_block;
   hipLaunchKernelGGL(k_bisect<T>, dim3((unsigned)blocks), dim3(256), 0, st, work, n, S, exp_in, lps, fail_flag);
@@ -150,18 +264,21 @@ hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, doub
 
 template <typename T>
 hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
-                                 int lps, hipStream_t st) {
+                                 int64_t max_n, hipStream_t st) {
   if (count <= 0 || total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bisect_prep_b<T>, dim3(count), dim3(256), 0, st, tab);
+  const int64_t G = bisect_grid_points(max_n);
+  hipLaunchKernelGGL(k_bisect_grid_b<T>, dim3((unsigned)((G + 255) / 256), (unsigned)count), dim3(256), 0, st, tab);
+  const int lps = bisect_lps(total);
   const int teams_per_block = 256 / lps;
   const int64_t blocks = (total + teams_per_block - 1) / teams_per_block;
   hipLaunchKernelGGL(k_bisect_b<T>, dim3((unsigned)blocks), dim3(256), 0, st, tab, vmat, voff, total, lps);
   return hipGetLastError();
 }
-template hipError_t launch_bisect_batched<float>(const BatchMat<float>*, int, const int*, const int64_t*, int64_t, int,
+template hipError_t launch_bisect_batched<float>(const BatchMat<float>*, int, const int*, const int64_t*, int64_t, int64_t,
                                                  hipStream_t);
 template hipError_t launch_bisect_batched<double>(const BatchMat<double>*, int, const int*, const int64_t*, int64_t,
-                                                  int, hipStream_t);
+                                                  int64_t, hipStream_t);
 template hipError_t launch_bisect<float>(const double*, const double*, int64_t, float*, double*, const int*, int,
                                          hipStream_t, const int*);
 template hipError_t launch_bisect<double>(const double*, const double*, int64_t, double*, double*, const int*, int,

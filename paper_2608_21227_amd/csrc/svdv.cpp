@@ -306,7 +306,7 @@ Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_w
   L.exp = take(8);
   L.d = take((size_t)N * 8);
   L.e = take((size_t)N * 8);
-  L.work = take((size_t)(2 * N + 2) * 8);
+  L.work = take((size_t)bisect_work_doubles(N) * 8);
   L.total = off;
   return L;
 }
@@ -452,7 +452,7 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   HIPCHK(launch_chase(ca, grid, st));
   g_timing.chase_mark(1, st);
   g_timing.mark(4, st);
-  if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 16, st, err));
+  if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 0, st, err));
   g_timing.mark(5, st);
   g_timing.valid = g_timing.enabled;
   return SVDV_OK;
@@ -545,7 +545,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
     bs_off[i] = take(sizeof(double) * Nv[i] * 3 * b);
     d_off[i] = take(sizeof(double) * Nv[i]);
     e_off[i] = take(sizeof(double) * Nv[i]);
-    wk_off[i] = take(sizeof(double) * (2 * Nv[i] + 2));
+    wk_off[i] = take(sizeof(double) * bisect_work_doubles(Nv[i]));
   }
   if (off > P.bytes) {
     if (P.mem) HIPCHK(hipFree(P.mem));
@@ -736,7 +736,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
     HIPCHK(launch_band_pack_batched<T>(dmats, cnt, b, maxN, st));
     HIPCHK(launch_chase_batched(L, grid, cnt, maxN, progress, nprog + 2, st));
     HIPCHK(launch_bisect_batched<T>(dmats, cnt, (const int*)(base + vmat_off), (const int64_t*)(base + voff_off),
-                                    total_vals, 16, st));
+                                    total_vals, maxN, st));
     return SVDV_OK;
   };
   return SVDV_OK;
@@ -930,8 +930,8 @@ int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_d
   double* work = (double*)(ws + L.work);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, expo, 0, (int64_t)1);
   const double* ee = e ? e : d;  // n == 1: e is never read
-  if (out_dtype == SVDV_F32) HIPCHK(launch_bisect<float>(d, ee, n, (float*)S, work, expo, 16, st));
-  else HIPCHK(launch_bisect<double>(d, ee, n, (double*)S, work, expo, 16, st));
+  if (out_dtype == SVDV_F32) HIPCHK(launch_bisect<float>(d, ee, n, (float*)S, work, expo, 0, st));
+  else HIPCHK(launch_bisect<double>(d, ee, n, (double*)S, work, expo, 0, st));
   return SVDV_OK;
 }
 
