@@ -34,6 +34,18 @@ struct RowMap {
   }
 };
 
+// Quotient a / b by a reciprocal and Newton-Raphson (Markstein's scheme): the
+// hardware reciprocal r ~ 1/b (about 24 correct bits) is refined once,
+// r += r (1 - b r), then q = a r gets one residual correction q += r (a - b q).
+// Valid for normal b whose reciprocal is normal; the result is within one unit
+// in the last place of the rounded quotient.
+__device__ __forceinline__ double nr_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
 // Wave-wide sums with DPP lane moves (quad permutes, row shifts and the row
 // broadcasts of wave64), the total collected in lane 63 and returned to every
 // lane through a scalar register, so all lanes see bitwise the same value.

@@ -29,13 +29,17 @@
 
 namespace svdv {
 
-// Optional step trace of group 0 (diagnostic builds only, -DSVDV_CHASE_TRACE):
-// eight timestamps per step of the 100 MHz real-time counter.
+// Optional step trace of one group (diagnostic builds only, -DSVDV_CHASE_TRACE,
+// group SVDV_TRACE_GROUP, default 0): eight timestamps per step of the 100 MHz
+// real-time counter.
 #ifdef SVDV_CHASE_TRACE
+#ifndef SVDV_TRACE_GROUP
+#define SVDV_TRACE_GROUP 0
+#endif
 __device__ uint64_t g_chase_trace[8 * 1024];
 #define CHASE_MARK_IF(cond, gi, t, k)                                          \
   do {                                                                         \
-    if ((cond) && (gi) == 0 && (t) < 1024)                                     \
+    if ((cond) && (gi) == SVDV_TRACE_GROUP && (t) < 1024)                      \
       g_chase_trace[(t) * 8 + (k)] = __builtin_amdgcn_s_memrealtime();         \
   } while (0)
 #else

@@ -61,20 +61,8 @@ __global__ void k_bisect_prep_b(const BatchMat<T>* __restrict__ tab) {
   bisect_prep_body(t.d, t.e, t.N, t.work);
 }
 
-// Quotient a / b by a reciprocal and Newton-Raphson (Markstein's scheme): the
-// hardware reciprocal r ~ 1/b (about 24 correct bits) is refined once,
-// r += r (1 - b r), then q = a r gets one residual correction q += r (a - b q).
-// Valid for normal b whose reciprocal is normal, which the choice of pivmin
-// guarantees for every pivot; the result is within one unit in the last place
-// of the rounded quotient.
-__device__ __forceinline__ double nr_div(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  const double q = a * r;
-  return fma(fma(-b, q, a), r, q);
-}
-
-// Sturm count of one shift x: the number of negative pivots.  d_i^2 and e_i^2 are
+// Sturm count of one shift x: the number of negative pivots (divisions by
+// nr_div: the choice of pivmin keeps every pivot and its reciprocal normal).  d_i^2 and e_i^2 are
 // fetched 8 steps at a time (wave-uniform addresses, so scalar loads that are in
 // flight while the previous 8 steps run).  pivmin is a power of two, so
 // |D+| < pivmin is decided exactly on the high 32 bits of D+; the sign bit of
