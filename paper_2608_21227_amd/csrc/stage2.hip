@@ -198,7 +198,7 @@ __device__ __forceinline__ ChaseArgs take_group(const ChaseArgs& L, int& gi) {
   __shared__ int s_ticket;
   if (threadIdx.x == 0) s_ticket = atomicAdd(L.ticket, 1);
   __syncthreads();
-  const int tk = s_ticket;
+  const int tk = __builtin_amdgcn_readfirstlane(s_ticket);  // uniform: keep the schedule scalar
   __syncthreads();
   if (tk >= L.total) {
     gi = -1;
@@ -601,14 +601,15 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs L) {
 // ---------------------------------------------------------------------------
 //
 // Waves 0..W-1 only compute (wave i runs task t-3i of sweep s0+i at step t);
-// the kSpecMovers waves after them move rows, during the tasks of the same
-// step.  At step t every mover thread
-//   1. waits for its own loads and stores of step t-1,
-//   2. (one thread) publishes the progress whose rows were stored at step t-2
-//      (all mover threads waited for those stores before the last barrier),
-//   3. writes the rows of step t+1, loaded at step t-1, into the window,
-//   4. stores the rows no sweep of the group touches after step t-1,
-//   5. waits until the predecessor group finished the tasks step t+2 depends
+// the kSpecMovers = 2 waves after them move rows, during the tasks of the same
+// step, side by side.  At step t the storer wave
+//   1. waits for its own stores of step t-1,
+//   2. (one lane) publishes the progress whose rows were stored at step t-2,
+//   3. stores the rows no sweep of the group touches after step t-1;
+// and the loader wave
+//   1. waits for its own loads of step t-1 and writes those rows (needed at
+//      step t+1) into the window,
+//   2. waits until the predecessor group finished the tasks step t+2 depends
 //      on, and requests the rows of step t+2.
 // One workgroup barrier ends a step.  Rows written in (3) are beyond every row
 // the tasks of step t touch, and rows stored in (4) are below them, so the
@@ -626,16 +627,17 @@ size_t chase_spec_lds_bytes(int b, int W) {
 
 template <int B>
 __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(ChaseArgs L) {
-  constexpr int RW = 3 * B, RS = RW + 2, MT = 64 * kSpecMovers;
-  constexpr int KP = (B * RW / 2 + MT - 1) / MT;  // pairs of doubles per mover thread for B rows
+  constexpr int RW = 3 * B, RS = RW + 2, MT = 64;
+  constexpr int KP = (B * RW / 2 + MT - 1) / MT;  // pairs of doubles per mover lane for B rows
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_flag;
   const int W = L.W;
   const int R = spec_rows(B, W);
   lds_f64* win = (lds_f64*)lds;
-  const int wv = threadIdx.x >> 6, tid = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), tid = threadIdx.x;  // wv: wave-uniform
   const bool mover = wv >= W;
-  const int mt = tid - 64 * W;  // mover thread index (valid when mover)
+  const bool storer = wv == W;  // the first mover wave stores and publishes, the second loads
+  const int mt = tid & 63;      // lane within the mover wave
   for (int e = tid; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
 
   for (;;) {
@@ -713,32 +715,37 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
         buf[k].y = ok ? bld(src + 2 * k * MT + 1) : 0.0;
       }
     };
-    auto pair_lds = [&](int s_r0, int q) -> lds_f64x2* {
-      int sl = s_r0 + q / (RW / 2);
+    // pair k of this thread: row prow[k] of the block, columns pcol[k], pcol[k] + 1
+    // (the same for every block, so computed once)
+    int prow[KP], pcol[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int q = mt + k * MT;
+      prow[k] = q / (RW / 2);
+      pcol[k] = 2 * (q % (RW / 2));
+    }
+    auto pair_lds = [&](int s_r0, int k) -> lds_f64x2* {
+      int sl = s_r0 + prow[k];
       sl = sl >= R ? sl - R : sl;
-      return (lds_f64x2*)(win + sl * RS + 2 * (q % (RW / 2)));
+      return (lds_f64x2*)(win + sl * RS + pcol[k]);
     };
     auto mv_fill = [&](int64_t r0, int64_t r1, const f64x2 (&buf)[KP]) {
-      const int np = (int)(r1 - r0) * (RW / 2);
+      const int rows = (int)(r1 - r0);
       const int s_r0 = slot(r0);
 #pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        const int q = mt + k * MT;
-        if (q < np) *pair_lds(s_r0, q) = buf[k];
-      }
+      for (int k = 0; k < KP; ++k)
+        if (prow[k] < rows) *pair_lds(s_r0, k) = buf[k];
     };
     auto mv_store = [&](int64_t r0, int64_t r1) {
       // up to B rows per batch (more only when the last sweep starts): LDS reads, then stores
       for (int64_t rb = r0; rb < r1; rb += B) {
         const int64_t re = r1 - rb < B ? r1 : rb + B;
         const int np = (int)(re - rb) * (RW / 2);
+        const int rows = (int)(re - rb);
         const int s_r0 = slot(rb);
         f64x2 vals[KP];
 #pragma unroll
-        for (int k = 0; k < KP; ++k) {
-          const int q = mt + k * MT;
-          vals[k] = q < np ? *pair_lds(s_r0, q) : f64x2{0.0, 0.0};
-        }
+        for (int k = 0; k < KP; ++k) vals[k] = prow[k] < rows ? *pair_lds(s_r0, k) : f64x2{0.0, 0.0};
         double* dst = a.Bs + rb * RW + 2 * mt;
 #pragma unroll
         for (int k = 0; k < KP; ++k)
@@ -749,7 +756,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
       }
     };
     // prologue: rows of steps 0 and 1, loaded directly
-    if (mover) {
+    if (mover && !storer) {
       wait_prev(4);
       if (!s_flag) {
         const int64_t hi1 = front_end(1);
@@ -779,11 +786,11 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
           }
         }
         CHASE_MARK(gi, t, 1);
-      } else {
-        // 1. own loads and stores of step t-1 complete
+      } else if (storer) {
+        // 1. own stores of step t-1 complete
         __builtin_amdgcn_s_waitcnt(0);
         CHASE_MARK_IF(mt == 0, gi, t, 3);
-        // 2. publish: rows stored at step t-2 are complete in every mover thread
+        // 2. publish: the rows stored at step t-2 are long complete
         if (mt == 0 && t >= 2) {
           int P = done_after(t - 3 >= 0 ? t - 3 : -1);
           const int br = by_rows(lo_hist[1]);
@@ -794,9 +801,7 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
             __hip_atomic_store(&a.progress[gi], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        // 3. rows of step t+1 (requested at step t-1) into the window
-        if (t >= 1) mv_fill(front_end(t), front_end(t + 1), regs);
-        // 4. store the rows final after step t-1
+        // 3. store the rows final after step t-1
         if (t >= 1) {
           const int64_t nlo = final_after(t - 1);
           mv_store(lo, nlo);
@@ -806,7 +811,11 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
         lo_hist[1] = lo_hist[0];
         lo_hist[0] = lo;
         CHASE_MARK_IF(mt == 0, gi, t, 4);
-        // 5. rows of step t+2
+      } else {
+        // 1. own loads of step t-1 complete; their rows (needed at step t+1) into the window
+        __builtin_amdgcn_s_waitcnt(0);
+        if (t >= 1) mv_fill(front_end(t), front_end(t + 1), regs);
+        // 2. rows of step t+2
         wait_prev(t + 5);
         CHASE_MARK_IF(mt == 0, gi, t, 5);
         if (!s_flag) mv_load(front_end(t + 1), front_end(t + 2), regs);
@@ -816,13 +825,13 @@ __global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(C
       CHASE_MARK(gi, t, 2);
     }
     // epilogue: store the rest of the window, then mark the group complete
-    if (mover) {
+    if (storer) {
       __builtin_amdgcn_s_waitcnt(0);
       mv_store(lo, front_end(tend));
       __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
-    if (mover && mt == 0 && !s_flag)
+    if (storer && mt == 0 && !s_flag)
       __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }

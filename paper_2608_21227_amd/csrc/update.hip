@@ -196,8 +196,15 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
   for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
     const int i = e / CB, col = e - i * CB;
     T acc = T(0);
-    if (i < k)
-      for (int l = 0; l <= i; ++l) acc += Tm[l + (int64_t)i * a.ldt] * Zs[l * CB + col];
+    if (i < k) {
+      // all T loads of the sum issued together (one cache round trip, not KR in a row)
+      T tv[KR];
+#pragma unroll
+      for (int l = 0; l < KR; ++l) tv[l] = l <= i ? Tm[l + (int64_t)i * a.ldt] : T(0);
+#pragma unroll
+      for (int l = 0; l < KR; ++l)
+        if (l <= i) acc += tv[l] * Zs[l * CB + col];
+    }
     Zp[e] = acc;
   }
   __syncthreads();
@@ -384,8 +391,15 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_stream(LarfbArgs<T> a) {
   for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
     const int i = e / CB, col = e - i * CB;
     T acc = T(0);
-    if (i < k)
-      for (int l = 0; l <= i; ++l) acc += Tm[l + (int64_t)i * a.ldt] * Zs[l * CB + col];
+    if (i < k) {
+      // all T loads of the sum issued together (one cache round trip, not KR in a row)
+      T tv[KR];
+#pragma unroll
+      for (int l = 0; l < KR; ++l) tv[l] = l <= i ? Tm[l + (int64_t)i * a.ldt] : T(0);
+#pragma unroll
+      for (int l = 0; l < KR; ++l)
+        if (l <= i) acc += tv[l] * Zs[l * CB + col];
+    }
     Zp[e] = acc;
   }
   __syncthreads();
