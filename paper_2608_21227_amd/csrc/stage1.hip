@@ -350,9 +350,35 @@ __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
 }
 
 // Batched form: one single-chunk panel per matrix, matrix blockIdx.x of the table.
+// A single chunk shorter than the capacity (the upper levels of a TSQR tree, the
+// panels of small or nearly finished matrices) runs the same body with fewer rows
+// per lane -- 2, 8 or 16, the fewest that hold it -- so that the per-column work
+// scales with the rows present, not with the capacity.  Returns the rows per lane
+// to use (RPT itself when no smaller tier applies).
+template <int RPT>
+__host__ __device__ inline int chunk_tier(int P, int64_t h) {
+  if (P != 1) return RPT;
+  if (RPT > 2 && h <= 64 * 2) return 2;
+  if (RPT > 8 && h <= 64 * 8) return 8;
+  if (RPT > 16 && h <= 64 * 16) return 16;
+  return RPT;
+}
+
 template <typename T, int TILE, int RPT>
 __global__ __launch_bounds__(1024) void k_chunk_qr_b(const ChunkQRArgs<T>* __restrict__ tab) {
-  chunk_qr_body<T, TILE, RPT>(tab[blockIdx.x], 0);
+  const ChunkQRArgs<T>& a = tab[blockIdx.x];
+  switch (chunk_tier<RPT>(a.P, a.h)) {  // the same choice as a single call
+    case 2:
+      if constexpr (RPT > 2) { chunk_qr_body<T, TILE, 2>(a, 0); return; }
+      break;
+    case 8:
+      if constexpr (RPT > 8) { chunk_qr_body<T, TILE, 8>(a, 0); return; }
+      break;
+    case 16:
+      if constexpr (RPT > 16) { chunk_qr_body<T, TILE, 16>(a, 0); return; }
+      break;
+  }
+  chunk_qr_body<T, TILE, RPT>(a, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,6 +492,16 @@ static hipError_t launch_cqr(const ChunkQRArgs<T>& a, hipStream_t st) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     configured = true;
+  }
+  const int tier = chunk_tier<RPT>(a.P, a.h);
+  if constexpr (RPT > 2) {
+    if (tier == 2) return launch_cqr<T, TILE, 2>(a, st);
+  }
+  if constexpr (RPT > 8) {
+    if (tier == 8) return launch_cqr<T, TILE, 8>(a, st);
+  }
+  if constexpr (RPT > 16) {
+    if (tier == 16) return launch_cqr<T, TILE, 16>(a, st);
   }
   hipLaunchKernelGGL((k_chunk_qr<T, TILE, RPT>), dim3(a.P), dim3(1024), lds, st, a);
   return hipGetLastError();
