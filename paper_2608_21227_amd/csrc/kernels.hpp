@@ -121,8 +121,9 @@ hipError_t launch_stage_in_batched(const BatchMat<T>* tab, int count, unsigned l
 template <typename T>
 hipError_t launch_band_pack_batched(const BatchMat<T>* tab, int count, int b, int64_t max_n, hipStream_t st);
 template <typename T>
+// min_rows / max_rows: the smallest and largest panel height h of the step's matrices.
 hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,
-                                int64_t max_ncols, hipStream_t st);
+                                int64_t max_ncols, int64_t min_rows, int64_t max_rows, hipStream_t st);
 template <typename T> hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,

@@ -581,6 +581,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
   std::vector<LarfbArgs<T>> uq(cnt * steps), ul(cnt * steps);
   std::vector<int> n_qr(steps, 0), n_lq(steps, 0), vec_qr(steps, 1), vec_lq(steps, 1);
   std::vector<int64_t> mc_qr(steps, 0), mc_lq(steps, 0);
+  std::vector<int64_t> lo_qr(steps, INT64_MAX), hi_qr(steps, 0), lo_lq(steps, INT64_MAX), hi_lq(steps, 0);
   for (int64_t k = 0; k < steps; ++k) {
     const int64_t k0 = k * b;
     for (int i = 0; i < cnt; ++i) {
@@ -619,6 +620,10 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         u.vec = larfb_vec_ok(u);
         vec_qr[k] &= u.vec;
         mc_qr[k] = std::max<int64_t>(mc_qr[k], u.col1 - u.col0);
+        if (u.col1 > u.col0) {
+          lo_qr[k] = std::min<int64_t>(lo_qr[k], h);
+          hi_qr[k] = std::max<int64_t>(hi_qr[k], h);
+        }
         n_qr[k] = i + 1;
       }
       const int64_t c1 = k0 + b;
@@ -652,6 +657,10 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         u.vec = larfb_vec_ok(u);
         vec_lq[k] &= u.vec;
         mc_lq[k] = std::max<int64_t>(mc_lq[k], u.col1 - u.col0);
+        if (u.col1 > u.col0) {
+          lo_lq[k] = std::min<int64_t>(lo_lq[k], h);
+          hi_lq[k] = std::max<int64_t>(hi_lq[k], h);
+        }
         n_lq[k] = i + 1;
       }
     }
@@ -726,11 +735,11 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
     for (int64_t k = 0; k < steps; ++k) {
       HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + qr_off) + k * cnt, n_qr[k], st));
       HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_qr[k], (const LarfbArgs<T>*)(base + uq_off) + k * cnt,
-                                     n_qr[k], mc_qr[k], st));
+                                     n_qr[k], mc_qr[k], lo_qr[k], hi_qr[k], st));
       if (n_lq[k] > 0) {
         HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + lq_off) + k * cnt, n_lq[k], st));
         HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_lq[k], (const LarfbArgs<T>*)(base + ul_off) + k * cnt,
-                                       n_lq[k], mc_lq[k], st));
+                                       n_lq[k], mc_lq[k], lo_lq[k], hi_lq[k], st));
       }
     }
     HIPCHK(launch_band_pack_batched<T>(dmats, cnt, b, maxN, st));

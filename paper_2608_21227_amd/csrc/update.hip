@@ -267,11 +267,13 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
 // Batched form: matrix blockIdx.z of the table (single-chunk panels); strips past
 // that matrix's columns return at once (before any barrier).
 template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
-__global__ void __launch_bounds__(NW * 64) k_larfb_reg_b(const LarfbArgs<T>* __restrict__ tab) {
+__global__ void __launch_bounds__(NW * 64) k_larfb_reg_b(const LarfbArgs<T>* __restrict__ tab, int64_t h_lo,
+                                                         int64_t h_hi) {
   const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.z * gridDim.x, (int64_t)gridDim.x * gridDim.z);
   const int strip = (int)(id % gridDim.x);
   const LarfbArgs<T>& a = tab[id / gridDim.x];
-  if (a.col0 + (int64_t)strip * IB * 16 >= a.col1 || a.k <= 0) return;
+  // matrices of height in (h_lo, h_hi] only (the others are another launch's)
+  if (a.col0 + (int64_t)strip * IB * 16 >= a.col1 || a.k <= 0 || a.h <= h_lo || a.h > h_hi) return;
   larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, strip, 0);
 }
 
@@ -465,6 +467,69 @@ static hipError_t launch_larfb_reg(const LarfbArgs<T>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Single chunks of at most kSmallUpdateRows rows (the upper levels of a TSQR tree,
+// small or nearly finished matrices, batches of small matrices) use the register
+// strip with 4 waves of 8 slabs (256 threads) at tile 16, whatever the configured
+// thread count: four workgroups fit on a CU instead of one, and a strip holds
+// exactly such a chunk.  Single and batched calls make the same choice per matrix.
+constexpr int kSmallUpdateRows = 512;
+template <typename T>
+inline bool small_update_ok(int tile, int ib) { return tile == 16 && (sizeof(T) == 4 ? ib <= 2 : ib == 1); }
+inline bool small_update_rows(int P, int64_t h) { return P == 1 && h <= kSmallUpdateRows; }
+
+template <typename T, int IB, bool VEC, int PREC>
+static hipError_t launch_larfb_small(const LarfbArgs<T>& a, hipStream_t st) {
+  constexpr size_t lds = larfb_lds<T>(1, IB, 4);
+  const int64_t ncols = a.col1 - a.col0;
+  const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), 1);
+  hipLaunchKernelGGL((k_larfb_reg<T, 1, IB, 4, 8, VEC, PREC>), grid, dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+template <typename T, int IB>
+static hipError_t launch_larfb_small_ib(const LarfbArgs<T>& a, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    switch (a.prec * 2 + (a.vec ? 1 : 0)) {
+      case 0: return launch_larfb_small<T, IB, false, 0>(a, st);
+      case 1: return launch_larfb_small<T, IB, true, 0>(a, st);
+      case 4: return launch_larfb_small<T, IB, false, 2>(a, st);
+      case 5: return launch_larfb_small<T, IB, true, 2>(a, st);
+      case 6: return launch_larfb_small<T, IB, false, 3>(a, st);
+      case 7: return launch_larfb_small<T, IB, true, 3>(a, st);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    if (a.prec != 0) return hipErrorInvalidValue;
+    return launch_larfb_small<T, IB, false, 0>(a, st);
+  }
+}
+
+template <typename T, int IB, bool VEC, int PREC>
+static hipError_t launch_larfb_small_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, hipStream_t st) {
+  constexpr size_t lds = larfb_lds<T>(1, IB, 4);
+  const dim3 grid((unsigned)((max_ncols + IB * 16 - 1) / (IB * 16)), 1, (unsigned)count);
+  hipLaunchKernelGGL((k_larfb_reg_b<T, 1, IB, 4, 8, VEC, PREC>), grid, dim3(256), lds, st, tab, (int64_t)0,
+                     (int64_t)kSmallUpdateRows);
+  return hipGetLastError();
+}
+template <typename T, int IB>
+static hipError_t launch_larfb_small_b_ib(int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t mc,
+                                          hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    switch (prec * 2 + (vec ? 1 : 0)) {
+      case 0: return launch_larfb_small_b<T, IB, false, 0>(tab, count, mc, st);
+      case 1: return launch_larfb_small_b<T, IB, true, 0>(tab, count, mc, st);
+      case 4: return launch_larfb_small_b<T, IB, false, 2>(tab, count, mc, st);
+      case 5: return launch_larfb_small_b<T, IB, true, 2>(tab, count, mc, st);
+      case 6: return launch_larfb_small_b<T, IB, false, 3>(tab, count, mc, st);
+      case 7: return launch_larfb_small_b<T, IB, true, 3>(tab, count, mc, st);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    if (prec != 0) return hipErrorInvalidValue;
+    return launch_larfb_small_b<T, IB, false, 0>(tab, count, mc, st);
+  }
+}
+
 template <typename T, int KT, int IB, int NW>
 static hipError_t launch_larfb_stream(const LarfbArgs<T>& a, hipStream_t st) {
   constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
@@ -531,7 +596,8 @@ static hipError_t launch_larfb_kt(int nw, int ib, const LarfbArgs<T>& a, hipStre
 }
 
 template <typename T, int KT, int IB, int NW, bool VEC, int PREC>
-static hipError_t launch_larfb_reg_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, hipStream_t st) {
+static hipError_t launch_larfb_reg_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, int64_t h_lo,
+                                     hipStream_t st) {
   constexpr int SPW = larfb_spw(KT * 16, NW);
   constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
   static bool configured = false;
@@ -542,27 +608,28 @@ static hipError_t launch_larfb_reg_b(const LarfbArgs<T>* tab, int count, int64_t
     configured = true;
   }
   const dim3 grid((unsigned)((max_ncols + IB * 16 - 1) / (IB * 16)), 1, (unsigned)count);
-  hipLaunchKernelGGL((k_larfb_reg_b<T, KT, IB, NW, SPW, VEC, PREC>), grid, dim3(NW * 64), lds, st, tab);
+  hipLaunchKernelGGL((k_larfb_reg_b<T, KT, IB, NW, SPW, VEC, PREC>), grid, dim3(NW * 64), lds, st, tab, h_lo,
+                     (int64_t)INT64_MAX);
   return hipGetLastError();
 }
 
 template <typename T, int KT, int IB, int NW>
 static hipError_t launch_larfb_b_nw(int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t max_ncols,
-                                    hipStream_t st) {
+                                    int64_t h_lo, hipStream_t st) {
   if constexpr (larfb_reg_valid<T>(KT, IB, NW)) {
     if constexpr (sizeof(T) == 4) {
       switch (prec * 2 + (vec ? 1 : 0)) {
-        case 0: return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, st);
-        case 1: return launch_larfb_reg_b<T, KT, IB, NW, true, 0>(tab, count, max_ncols, st);
-        case 4: return launch_larfb_reg_b<T, KT, IB, NW, false, 2>(tab, count, max_ncols, st);
-        case 5: return launch_larfb_reg_b<T, KT, IB, NW, true, 2>(tab, count, max_ncols, st);
-        case 6: return launch_larfb_reg_b<T, KT, IB, NW, false, 3>(tab, count, max_ncols, st);
-        case 7: return launch_larfb_reg_b<T, KT, IB, NW, true, 3>(tab, count, max_ncols, st);
+        case 0: return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, h_lo, st);
+        case 1: return launch_larfb_reg_b<T, KT, IB, NW, true, 0>(tab, count, max_ncols, h_lo, st);
+        case 4: return launch_larfb_reg_b<T, KT, IB, NW, false, 2>(tab, count, max_ncols, h_lo, st);
+        case 5: return launch_larfb_reg_b<T, KT, IB, NW, true, 2>(tab, count, max_ncols, h_lo, st);
+        case 6: return launch_larfb_reg_b<T, KT, IB, NW, false, 3>(tab, count, max_ncols, h_lo, st);
+        case 7: return launch_larfb_reg_b<T, KT, IB, NW, true, 3>(tab, count, max_ncols, h_lo, st);
       }
       return hipErrorInvalidValue;
     } else {
       if (prec != 0) return hipErrorInvalidValue;
-      return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, st);
+      return launch_larfb_reg_b<T, KT, IB, NW, false, 0>(tab, count, max_ncols, h_lo, st);
     }
   } else {
     return hipErrorInvalidConfiguration;  // the batched path needs the register-strip form
@@ -571,38 +638,46 @@ static hipError_t launch_larfb_b_nw(int prec, int vec, const LarfbArgs<T>* tab, 
 
 template <typename T, int KT, int IB>
 static hipError_t launch_larfb_b_ib(int nw, int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t mc,
-                                    hipStream_t st) {
+                                    int64_t h_lo, hipStream_t st) {
   switch (nw) {
-    case 1: return launch_larfb_b_nw<T, KT, IB, 1>(prec, vec, tab, count, mc, st);
-    case 2: return launch_larfb_b_nw<T, KT, IB, 2>(prec, vec, tab, count, mc, st);
-    case 4: return launch_larfb_b_nw<T, KT, IB, 4>(prec, vec, tab, count, mc, st);
-    case 8: return launch_larfb_b_nw<T, KT, IB, 8>(prec, vec, tab, count, mc, st);
-    case 16: return launch_larfb_b_nw<T, KT, IB, 16>(prec, vec, tab, count, mc, st);
+    case 1: return launch_larfb_b_nw<T, KT, IB, 1>(prec, vec, tab, count, mc, h_lo, st);
+    case 2: return launch_larfb_b_nw<T, KT, IB, 2>(prec, vec, tab, count, mc, h_lo, st);
+    case 4: return launch_larfb_b_nw<T, KT, IB, 4>(prec, vec, tab, count, mc, h_lo, st);
+    case 8: return launch_larfb_b_nw<T, KT, IB, 8>(prec, vec, tab, count, mc, h_lo, st);
+    case 16: return launch_larfb_b_nw<T, KT, IB, 16>(prec, vec, tab, count, mc, h_lo, st);
   }
   return hipErrorInvalidConfiguration;
 }
 
 template <typename T, int KT>
 static hipError_t launch_larfb_b_kt(int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count, int64_t mc,
-                                    hipStream_t st) {
+                                    int64_t h_lo, hipStream_t st) {
   switch (ib) {
-    case 1: return launch_larfb_b_ib<T, KT, 1>(nw, prec, vec, tab, count, mc, st);
-    case 2: return launch_larfb_b_ib<T, KT, 2>(nw, prec, vec, tab, count, mc, st);
-    case 4: return launch_larfb_b_ib<T, KT, 4>(nw, prec, vec, tab, count, mc, st);
-    case 8: return launch_larfb_b_ib<T, KT, 8>(nw, prec, vec, tab, count, mc, st);
+    case 1: return launch_larfb_b_ib<T, KT, 1>(nw, prec, vec, tab, count, mc, h_lo, st);
+    case 2: return launch_larfb_b_ib<T, KT, 2>(nw, prec, vec, tab, count, mc, h_lo, st);
+    case 4: return launch_larfb_b_ib<T, KT, 4>(nw, prec, vec, tab, count, mc, h_lo, st);
+    case 8: return launch_larfb_b_ib<T, KT, 8>(nw, prec, vec, tab, count, mc, h_lo, st);
   }
   return hipErrorInvalidConfiguration;
 }
 
 template <typename T>
 hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,
-                                int64_t max_ncols, hipStream_t st) {
+                                int64_t max_ncols, int64_t min_rows, int64_t max_rows, hipStream_t st) {
   if (count <= 0 || max_ncols <= 0) return hipSuccess;
+  int64_t h_lo = 0;  // the general launch takes the matrices taller than h_lo
+  if (small_update_ok<T>(tile, ib) && min_rows <= kSmallUpdateRows) {
+    hipError_t e = ib == 1 ? launch_larfb_small_b_ib<T, 1>(prec, vec, tab, count, max_ncols, st)
+                           : launch_larfb_small_b_ib<T, 2>(prec, vec, tab, count, max_ncols, st);
+    if (e != hipSuccess) return e;
+    if (max_rows <= kSmallUpdateRows) return hipSuccess;
+    h_lo = kSmallUpdateRows;
+  }
   switch (tile) {
-    case 16: return launch_larfb_b_kt<T, 1>(nw, ib, prec, vec, tab, count, max_ncols, st);
-    case 32: return launch_larfb_b_kt<T, 2>(nw, ib, prec, vec, tab, count, max_ncols, st);
-    case 64: return launch_larfb_b_kt<T, 4>(nw, ib, prec, vec, tab, count, max_ncols, st);
-    case 128: return launch_larfb_b_kt<T, 8>(nw, ib, prec, vec, tab, count, max_ncols, st);
+    case 16: return launch_larfb_b_kt<T, 1>(nw, ib, prec, vec, tab, count, max_ncols, h_lo, st);
+    case 32: return launch_larfb_b_kt<T, 2>(nw, ib, prec, vec, tab, count, max_ncols, h_lo, st);
+    case 64: return launch_larfb_b_kt<T, 4>(nw, ib, prec, vec, tab, count, max_ncols, h_lo, st);
+    case 128: return launch_larfb_b_kt<T, 8>(nw, ib, prec, vec, tab, count, max_ncols, h_lo, st);
   }
   return hipErrorInvalidValue;
 }
@@ -610,6 +685,8 @@ hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, con
 template <typename T>
 hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st) {
   if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
+  if (small_update_ok<T>(tile, ib) && small_update_rows(a.P, a.h))
+    return ib == 1 ? launch_larfb_small_ib<T, 1>(a, st) : launch_larfb_small_ib<T, 2>(a, st);
   switch (tile) {
     case 16: return launch_larfb_kt<T, 1>(nw, ib, a, st);
     case 32: return launch_larfb_kt<T, 2>(nw, ib, a, st);
@@ -622,8 +699,8 @@ hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStre
 template hipError_t launch_larfb<float>(int, int, int, const LarfbArgs<float>&, hipStream_t);
 template hipError_t launch_larfb<double>(int, int, int, const LarfbArgs<double>&, hipStream_t);
 template hipError_t launch_larfb_batched<float>(int, int, int, int, int, const LarfbArgs<float>*, int, int64_t,
-                                                hipStream_t);
+                                                int64_t, int64_t, hipStream_t);
 template hipError_t launch_larfb_batched<double>(int, int, int, int, int, const LarfbArgs<double>*, int, int64_t,
-                                                 hipStream_t);
+                                                 int64_t, int64_t, hipStream_t);
 
 }  // namespace svdv
