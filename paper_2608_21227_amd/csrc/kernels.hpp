@@ -125,6 +125,13 @@ template <typename T>
 hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,
                                 int64_t max_ncols, int64_t min_rows, int64_t max_rows, hipStream_t st);
 template <typename T> hipError_t launch_larfb(int tile, int nw, int ib, const LarfbArgs<T>& a, hipStream_t st);
+// Split form of one panel taller than a register strip (a.P == 1, a.h rows):
+// row blocks of the strip capacity; zw: larfb_split_work() elements of device
+// workspace.  Available when the register-strip kernel is (larfb_split_ok).
+template <typename T> bool larfb_split_ok(int tile, int nw, int ib);
+template <typename T> int64_t larfb_split_work(int tile, int nw, int ib, int64_t h, int64_t ncols);
+template <typename T>
+hipError_t launch_larfb_split(int tile, int nw, int ib, const LarfbArgs<T>& a, T* zw, hipStream_t st);
 template <typename T>
 hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* Bs, int64_t ldb, const int* exp_in,
                             int unscale, hipStream_t st);

@@ -958,11 +958,16 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
   int rc = check_config_impl(h, w, dtype, c);
   if (rc) return rc;
   if (k > c.tile) return fail(SVDV_ERR_UNSUPPORTED, "k exceeds cfg->tile");
-  const bool tall_ok = dtype == SVDV_F32 ? larfb_stream_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
-                                          : larfb_stream_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
-  if (vrows > 32768 / c.tile && c.update_precision != 0)
+  const bool tall = vrows > 32768 / c.tile;
+  // a tall panel runs split over row blocks when the register strip exists for this
+  // configuration, else the streaming form
+  const bool split = tall && (dtype == SVDV_F32 ? larfb_split_ok<float>(c.tile, c.threads / 64, c.inner_block)
+                                                : larfb_split_ok<double>(c.tile, c.threads / 64, c.inner_block));
+  const bool stream_ok = dtype == SVDV_F32 ? larfb_stream_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
+                                            : larfb_stream_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
+  if (tall && c.update_precision != 0)
     return fail(SVDV_ERR_UNSUPPORTED, "BF16/FP16 updates need a reflector length of at most 32768 / cfg->tile");
-  if (vrows > 32768 / c.tile && !tall_ok)
+  if (tall && !split && !stream_ok)
     return fail(SVDV_ERR_UNSUPPORTED, "reflector length exceeds 32768 / cfg->tile, which this configuration "
                                       "(threads, inner_block) only handles in registers");
   hipStream_t st = (hipStream_t)stream;
@@ -983,6 +988,14 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
     a.k = (int32_t)k;
     a.vec = larfb_vec_ok(a);
     a.prec = c.update_precision;
+    if (split) {
+      const int64_t elems = larfb_split_work<T>(c.tile, c.threads / 64, c.inner_block, vrows, a.col1 - a.col0);
+      char* ws = nullptr;
+      const int wrc = get_workspace(st, (size_t)elems * sizeof(T), &ws);
+      if (wrc) return wrc;
+      HIPCHK(launch_larfb_split<T>(c.tile, c.threads / 64, c.inner_block, a, (T*)ws, st));
+      return SVDV_OK;
+    }
     HIPCHK(launch_larfb<T>(c.tile, c.threads / 64, c.inner_block, a, st));
     return SVDV_OK;
   };

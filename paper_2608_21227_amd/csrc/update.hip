@@ -20,6 +20,7 @@
 // share a column strip and split its rows, like the split-K "K" of Algorithm 2),
 // inner_block = IB (16-column MFMA tiles per workgroup, like "CPB").
 #include <algorithm>
+#include <type_traits>
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -95,8 +96,12 @@ __device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int H
 }
 
 // PREC 0: MFMA in T; PREC 2 / 3 (T = float): BF16 / FP16 operands, float32 accumulation.
-template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
-__device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int strip, const int c) {
+// MODE 0: the whole update of the strip.  Split over row blocks (a single panel
+// taller than the registers hold, see launch_larfb_tall): MODE 1 writes this row
+// block's Z = V^T C to zw[(c * strips + strip)] and stops; MODE 2 takes the
+// strip's Z' = T^T (sum of the blocks' Z) from zw[strip] and does pass 2 only.
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC, int MODE = 0>
+__device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int strip, const int c, T* zw = nullptr) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -122,8 +127,10 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
     if (s < nslab) {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
+      if constexpr (MODE != 2) {
 #pragma unroll
-      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+        for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+      }
     } else {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt)
@@ -142,7 +149,9 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
   for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
-  if constexpr (PREC == 0) {
+  if constexpr (MODE == 2) {
+    // Z' comes from the split form's reduction
+  } else if constexpr (PREC == 0) {
 #pragma unroll
     for (int j = 0; j < SPW; ++j)
 #pragma unroll
@@ -165,18 +174,20 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
   // A[m = row][k = reflector]: lane (g, nl) holds -V[q0 + nl][r], r = 4 kk + g (K = 4 per
   // instruction) or, for the 16x16x16 forms, r = 16 (kk / 4) + 4 g + kk % 4
   T va[SPW][KR / 4];
+  if constexpr (MODE != 1) {
 #pragma unroll
-  for (int j = 0; j < SPW; ++j) {
-    const int q = (wv + j * NW) * 16 + nl;
+    for (int j = 0; j < SPW; ++j) {
+      const int q = (wv + j * NW) * 16 + nl;
 #pragma unroll
-    for (int kk = 0; kk < KR / 4; ++kk) {
-      const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
-      va[j][kk] = (q < Hc && r < k) ? -V[q + (int64_t)r * a.ldv] : T(0);
+      for (int kk = 0; kk < KR / 4; ++kk) {
+        const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
+        va[j][kk] = (q < Hc && r < k) ? -V[q + (int64_t)r * a.ldv] : T(0);
+      }
     }
   }
 
   // ---------------- reduce the NW partials (fixed order) ----------------
-  {
+  if constexpr (MODE != 2) {
     T* mine = Zs + (size_t)wv * KR * CB;
 #pragma unroll
     for (int mt = 0; mt < KT; ++mt)
@@ -185,38 +196,48 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
 #pragma unroll
         for (int r = 0; r < 4; ++r) mine[(mt * 16 + acc_row<T>(g, r)) * CB + nt * 16 + nl] = Z[mt][nt][r];
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
-    T acc = Zs[e];
-    for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
-    Zs[e] = acc;
-  }
-  __syncthreads();
-  // ---------------- Z' = T^T Z (T upper triangular, k x k) ----------------
-  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
-    const int i = e / CB, col = e - i * CB;
-    T acc = T(0);
-    if (i < k) {
-      // all T loads of the sum issued together (one cache round trip, not KR in a row)
-      T tv[KR];
-#pragma unroll
-      for (int l = 0; l < KR; ++l) tv[l] = l <= i ? Tm[l + (int64_t)i * a.ldt] : T(0);
-#pragma unroll
-      for (int l = 0; l < KR; ++l)
-        if (l <= i) acc += tv[l] * Zs[l * CB + col];
+  if constexpr (MODE != 2) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+      T acc = Zs[e];
+      for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
+      Zs[e] = acc;
     }
-    Zp[e] = acc;
+    if constexpr (MODE == 1) {  // this row block's Z, for the split form's reduction
+      T* out = zw + ((int64_t)c * gridDim.x + strip) * (KR * CB);
+      for (int e = threadIdx.x; e < KR * CB; e += NW * 64) out[e] = Zs[(size_t)0 * KR * CB + e];
+      return;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  if constexpr (MODE == 0) {
+    // ---------------- Z' = T^T Z (T upper triangular, k x k) ----------------
+    for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+      const int i = e / CB, col = e - i * CB;
+      T acc = T(0);
+      if (i < k) {
+        // all T loads of the sum issued together (one cache round trip, not KR in a row)
+        T tv[KR];
+#pragma unroll
+        for (int l = 0; l < KR; ++l) tv[l] = l <= i ? Tm[l + (int64_t)i * a.ldt] : T(0);
+#pragma unroll
+        for (int l = 0; l < KR; ++l)
+          if (l <= i) acc += tv[l] * Zs[l * CB + col];
+      }
+      Zp[e] = acc;
+    }
+    __syncthreads();
+  }
 
   // ---------------- pass 2: C -= V Z', accumulated into the strip registers ----------------
   // B[k = reflector][n = column]: lane (g, nl) holds Z'[4 kk + g][16 nt + nl]
+  const T* zsrc = MODE == 2 ? zw + (int64_t)strip * (KR * CB) : Zp;
   T zb[KR / 4][IB];
 #pragma unroll
   for (int kk = 0; kk < KR / 4; ++kk) {
     const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
 #pragma unroll
-    for (int nt = 0; nt < IB; ++nt) zb[kk][nt] = Zp[r * CB + nt * 16 + nl];
+    for (int nt = 0; nt < IB; ++nt) zb[kk][nt] = zsrc[r * CB + nt * 16 + nl];
   }
 #pragma unroll
   for (int j = 0; j < SPW; ++j) {
@@ -262,6 +283,38 @@ template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC>
 __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.y * gridDim.x, (int64_t)gridDim.x * gridDim.y);
   larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, (int)(id % gridDim.x), (int)(id / gridDim.x));
+}
+
+// Split form of one tall panel (reflectors longer than a strip's registers hold):
+// row blocks of the register capacity, MODE 1 (partial Z per block) or MODE 2
+// (pass 2 with the reduced Z'), grid (strips, blocks).
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int MODE>
+__global__ void __launch_bounds__(NW * 64) k_larfb_split(LarfbArgs<T> a, T* zw) {
+  const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.y * gridDim.x, (int64_t)gridDim.x * gridDim.y);
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, 0, MODE>(a, (int)(id % gridDim.x), (int)(id / gridDim.x), zw);
+}
+
+// Z = sum of the P blocks' partial Z in block order, then Z' = T^T Z (T the panel's
+// k x k upper triangular factor); one workgroup per strip.
+template <typename T, int KT, int IB>
+__global__ void __launch_bounds__(256) k_larfb_split_z(const T* __restrict__ zpart, T* __restrict__ zprime, int P,
+                                                       const T* __restrict__ Tm, int64_t ldt, int k) {
+  constexpr int KR = KT * 16, CB = IB * 16;
+  __shared__ T Zs[KR * CB];
+  const int strip = blockIdx.x, nstrips = gridDim.x;
+  for (int e = threadIdx.x; e < KR * CB; e += blockDim.x) {
+    T acc = T(0);
+    for (int c = 0; c < P; ++c) acc += zpart[((int64_t)c * nstrips + strip) * (KR * CB) + e];
+    Zs[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KR * CB; e += blockDim.x) {
+    const int i = e / CB, col = e - i * CB;
+    T acc = T(0);
+    if (i < k)
+      for (int l = 0; l <= i; ++l) acc += Tm[l + (int64_t)i * ldt] * Zs[l * CB + col];
+    zprime[(int64_t)strip * (KR * CB) + e] = acc;
+  }
 }
 
 // Batched form: matrix blockIdx.z of the table (single-chunk panels); strips past
@@ -660,6 +713,118 @@ static hipError_t launch_larfb_b_kt(int nw, int ib, int prec, int vec, const Lar
   }
   return hipErrorInvalidConfiguration;
 }
+
+// ---- split form of one tall panel ----
+template <typename T, int KT, int IB, int NW, bool VEC>
+static hipError_t launch_larfb_split_v(const LarfbArgs<T>& a0, T* zw, hipStream_t st) {
+  constexpr int SPW = larfb_spw(KT * 16, NW), KR = KT * 16, CB = IB * 16;
+  constexpr int64_t R0 = (int64_t)SPW * NW * 16;  // rows of one block (the register capacity)
+  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  LarfbArgs<T> a = a0;
+  a.chunk_rows = R0;
+  a.P = (int32_t)((a0.h + R0 - 1) / R0);
+  a.rm.chunk_stride = R0;  // block c holds rows c R0 .. of the single panel
+  const int64_t nstrips = (a.col1 - a.col0 + CB - 1) / CB;
+  T* zpart = zw;
+  T* zprime = zw + (int64_t)a.P * nstrips * KR * CB;
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_split<T, KT, IB, NW, SPW, VEC, 1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_larfb_split<T, KT, IB, NW, SPW, VEC, 2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  const dim3 grid((unsigned)nstrips, (unsigned)a.P);
+  hipLaunchKernelGGL((k_larfb_split<T, KT, IB, NW, SPW, VEC, 1>), grid, dim3(NW * 64), lds, st, a, zpart);
+  hipLaunchKernelGGL((k_larfb_split_z<T, KT, IB>), dim3((unsigned)nstrips), dim3(256), 0, st, (const T*)zpart, zprime,
+                     (int)a.P, a.Tm, a.ldt, a.k);
+  hipLaunchKernelGGL((k_larfb_split<T, KT, IB, NW, SPW, VEC, 2>), grid, dim3(NW * 64), lds, st, a, zprime);
+  return hipGetLastError();
+}
+template <typename T, int KT, int IB, int NW>
+static hipError_t launch_larfb_split_nw(const LarfbArgs<T>& a, T* zw, hipStream_t st) {
+  if constexpr (larfb_reg_valid<T>(KT, IB, NW)) {
+    if constexpr (sizeof(T) == 4) {
+      if (a.vec) return launch_larfb_split_v<T, KT, IB, NW, true>(a, zw, st);
+    }
+    return launch_larfb_split_v<T, KT, IB, NW, false>(a, zw, st);
+  } else {
+    return hipErrorInvalidConfiguration;
+  }
+}
+template <typename T, int KT, int IB>
+static hipError_t launch_larfb_split_ib(int nw, const LarfbArgs<T>& a, T* zw, hipStream_t st) {
+  switch (nw) {
+    case 8: return launch_larfb_split_nw<T, KT, IB, 8>(a, zw, st);
+    case 16: return launch_larfb_split_nw<T, KT, IB, 16>(a, zw, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+template <typename T, int KT>
+static hipError_t launch_larfb_split_kt(int nw, int ib, const LarfbArgs<T>& a, T* zw, hipStream_t st) {
+  switch (ib) {
+    case 1: return launch_larfb_split_ib<T, KT, 1>(nw, a, zw, st);
+    case 2: return launch_larfb_split_ib<T, KT, 2>(nw, a, zw, st);
+    case 4: return launch_larfb_split_ib<T, KT, 4>(nw, a, zw, st);
+    case 8: return launch_larfb_split_ib<T, KT, 8>(nw, a, zw, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T>
+bool larfb_split_ok(int tile, int nw, int ib) {
+  const int kt = tile / 16;
+  auto ok = [&](auto KTc) {
+    constexpr int KT = decltype(KTc)::value;
+    switch (nw * 16 + ib) {
+      case 8 * 16 + 1: return larfb_reg_valid<T>(KT, 1, 8);
+      case 8 * 16 + 2: return larfb_reg_valid<T>(KT, 2, 8);
+      case 8 * 16 + 4: return larfb_reg_valid<T>(KT, 4, 8);
+      case 8 * 16 + 8: return larfb_reg_valid<T>(KT, 8, 8);
+      case 16 * 16 + 1: return larfb_reg_valid<T>(KT, 1, 16);
+      case 16 * 16 + 2: return larfb_reg_valid<T>(KT, 2, 16);
+      case 16 * 16 + 4: return larfb_reg_valid<T>(KT, 4, 16);
+      case 16 * 16 + 8: return larfb_reg_valid<T>(KT, 8, 16);
+    }
+    return false;
+  };
+  switch (kt) {
+    case 1: return ok(std::integral_constant<int, 1>{});
+    case 2: return ok(std::integral_constant<int, 2>{});
+    case 4: return ok(std::integral_constant<int, 4>{});
+    case 8: return ok(std::integral_constant<int, 8>{});
+  }
+  return false;
+}
+
+template <typename T>
+int64_t larfb_split_work(int tile, int nw, int ib, int64_t h, int64_t ncols) {
+  const int64_t R0 = (int64_t)larfb_spw(tile, nw) * nw * 16;
+  const int64_t P = (h + R0 - 1) / R0, CB = 16 * ib, nstrips = (ncols + CB - 1) / CB;
+  return (P + 1) * nstrips * tile * CB;
+}
+
+template <typename T>
+hipError_t launch_larfb_split(int tile, int nw, int ib, const LarfbArgs<T>& a, T* zw, hipStream_t st) {
+  if (a.col1 <= a.col0 || a.k <= 0) return hipSuccess;
+  if (a.prec != 0) return hipErrorInvalidValue;
+  switch (tile) {
+    case 16: return launch_larfb_split_kt<T, 1>(nw, ib, a, zw, st);
+    case 32: return launch_larfb_split_kt<T, 2>(nw, ib, a, zw, st);
+    case 64: return launch_larfb_split_kt<T, 4>(nw, ib, a, zw, st);
+    case 128: return launch_larfb_split_kt<T, 8>(nw, ib, a, zw, st);
+  }
+  return hipErrorInvalidValue;
+}
+template bool larfb_split_ok<float>(int, int, int);
+template bool larfb_split_ok<double>(int, int, int);
+template int64_t larfb_split_work<float>(int, int, int, int64_t, int64_t);
+template int64_t larfb_split_work<double>(int, int, int, int64_t, int64_t);
+template hipError_t launch_larfb_split<float>(int, int, int, const LarfbArgs<float>&, float*, hipStream_t);
+template hipError_t launch_larfb_split<double>(int, int, int, const LarfbArgs<double>&, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_larfb_batched(int tile, int nw, int ib, int prec, int vec, const LarfbArgs<T>* tab, int count,

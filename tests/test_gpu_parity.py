@@ -21,6 +21,21 @@ def _svdv():
     (100, 70, 16, 16, 64, 1), (256, 300, 32, 32, 256, 2), (513, 129, 64, 64, 128, 2), (77, 33, 7, 16, 64, 4),
     (200, 250, 128, 128, 256, 1)])
 def test_apply_qt_matches_explicit_product(dtype, side, h, w, k, tile, threads, ib):
+    _apply_qt_case(dtype, side, h, w, k, tile, threads, ib)
+
+
+# reflectors longer than 32768 / tile rows: split over row blocks of that many rows
+# (ragged last block, an exact multiple, fewer reflectors than the tile)
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("vr,other,k,tile,threads,ib", [
+    (1300, 70, 64, 64, 512, 2), (1024, 100, 64, 64, 1024, 1), (2500, 45, 20, 32, 512, 2), (4100, 33, 16, 16, 1024, 1),
+    (600, 140, 100, 128, 512, 1)])
+def test_apply_qt_tall_split(side, vr, other, k, tile, threads, ib):
+    h, w = (vr, other) if side == 0 else (other, vr)
+    _apply_qt_case("float32", side, h, w, k, tile, threads, ib)
+
+
+def _apply_qt_case(dtype, side, h, w, k, tile, threads, ib):
     torch = torch_cuda()
     svdv = _svdv()
     cfg = svdv.Config(tile=tile, threads=threads, inner_block=ib, sweep_width=1)
