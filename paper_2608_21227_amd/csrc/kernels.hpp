@@ -71,9 +71,19 @@ template <typename T>
 constexpr size_t larfb_lds(int KT, int IB, int NW) {
   return (size_t)(NW + 1) * (KT * 16) * (IB * 16) * sizeof(T);
 }
+// Register-strip kernel: the partial Z tiles, or (once Z' is formed) one 16-row
+// V slab per wave being transposed for pass 2 (rows padded by 4), then Z'.
+constexpr int64_t larfb_reg_lds_elems(int KT, int IB, int NW) {
+  const int64_t kr = KT * 16, cb = IB * 16;
+  return (NW * kr * cb > NW * 16 * (kr + 4) ? NW * kr * cb : NW * 16 * (kr + 4)) + kr * cb;
+}
+template <typename T>
+constexpr size_t larfb_reg_lds(int KT, int IB, int NW) {
+  return (size_t)larfb_reg_lds_elems(KT, IB, NW) * sizeof(T);
+}
 template <typename T>
 constexpr bool larfb_reg_valid(int KT, int IB, int NW) {
-  return larfb_reg_regs<T>(KT, IB, NW) <= larfb_reg_budget(NW) && larfb_lds<T>(KT, IB, NW) <= 128 * 1024;
+  return larfb_reg_regs<T>(KT, IB, NW) <= larfb_reg_budget(NW) && larfb_reg_lds<T>(KT, IB, NW) <= 128 * 1024;
 }
 template <typename T>
 constexpr bool larfb_stream_valid(int KT, int IB, int NW) {

@@ -96,17 +96,18 @@ __device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int H
 }
 
 // PREC 0: MFMA in T; PREC 2 / 3 (T = float): BF16 / FP16 operands, float32 accumulation.
-// MODE 0: the whole update of the strip.  Split over row blocks (a single panel
-// taller than the registers hold, see launch_larfb_tall): MODE 1 writes this row
-// block's Z = V^T C to zw[(c * strips + strip)] and stops; MODE 2 takes the
-// strip's Z' = T^T (sum of the blocks' Z) from zw[strip] and does pass 2 only.
+// MODE 0: the whole update of the strip.  MODE 2 (the split form of a single panel
+// taller than the registers hold): the strip's Z' = T^T V^T C comes from zw[strip],
+// written by the split form's first pass and reduction, and only pass 2 runs.
 template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC, int MODE = 0>
 __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int strip, const int c, T* zw = nullptr) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Zs = reinterpret_cast<T*>(smem_raw);  // [NW][KR][CB] partial sums; slot 0 then holds Z
-  T* Zp = Zs + (size_t)NW * KR * CB;       // [KR][CB] Z' = T^T Z
+  // [NW][KR][CB] partial sums (slot 0 then holds Z); in pass 2 the same space holds
+  // each wave's [16][KR + 4] V slab being transposed
+  T* Zs = reinterpret_cast<T*>(smem_raw);
+  T* Zp = Zs + (larfb_reg_lds_elems(KT, IB, NW) - KR * CB);  // [KR][CB] Z' = T^T Z
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, nl = lane & 15;
   const int64_t row0 = (int64_t)c * a.chunk_rows;
@@ -127,10 +128,8 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
     if (s < nslab) {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
-      if constexpr (MODE != 2) {
 #pragma unroll
-        for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
-      }
+      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
     } else {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt)
@@ -170,21 +169,10 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
         for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16x16<PREC>(vr[j][mt], cr[j][nt], Z[mt][nt]);
   }
 
-  // pass-2 operands (reflectors along K, rows along lanes), requested before the reduction
+  // pass-2 operand (reflectors along K, rows along lanes), formed per slab in pass 2
   // A[m = row][k = reflector]: lane (g, nl) holds -V[q0 + nl][r], r = 4 kk + g (K = 4 per
   // instruction) or, for the 16x16x16 forms, r = 16 (kk / 4) + 4 g + kk % 4
   T va[SPW][KR / 4];
-  if constexpr (MODE != 1) {
-#pragma unroll
-    for (int j = 0; j < SPW; ++j) {
-      const int q = (wv + j * NW) * 16 + nl;
-#pragma unroll
-      for (int kk = 0; kk < KR / 4; ++kk) {
-        const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
-        va[j][kk] = (q < Hc && r < k) ? -V[q + (int64_t)r * a.ldv] : T(0);
-      }
-    }
-  }
 
   // ---------------- reduce the NW partials (fixed order) ----------------
   if constexpr (MODE != 2) {
@@ -202,11 +190,6 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
       T acc = Zs[e];
       for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
       Zs[e] = acc;
-    }
-    if constexpr (MODE == 1) {  // this row block's Z, for the split form's reduction
-      T* out = zw + ((int64_t)c * gridDim.x + strip) * (KR * CB);
-      for (int e = threadIdx.x; e < KR * CB; e += NW * 64) out[e] = Zs[(size_t)0 * KR * CB + e];
-      return;
     }
     __syncthreads();
   }
@@ -246,6 +229,24 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
     AccT acc[IB];
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) acc[nt] = AccT{cr[j][nt][0], cr[j][nt][1], cr[j][nt][2], cr[j][nt][3]};
+    {
+      // vr[j][mt][i] = V[row acc_row(g, i)][reflector 16 mt + nl] of this slab (zero
+      // outside the chunk and past k), transposed through this wave's LDS slab:
+      // va[j][kk] needs row nl, reflector r(kk, g).  The Zs space is free here (Z'
+      // was formed behind a barrier) and each wave touches only its own slab.
+      T* buf = Zs + (size_t)wv * 16 * (KR + 4);
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) buf[acc_row<T>(g, i) * (KR + 4) + mt * 16 + nl] = vr[j][mt][i];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR / 4; ++kk) {
+        const int r = PREC == 0 ? 4 * kk + g : 16 * (kk / 4) + 4 * g + kk % 4;
+        va[j][kk] = -buf[nl * (KR + 4) + r];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
     if constexpr (PREC == 0) {
 #pragma unroll
       for (int kk = 0; kk < KR / 4; ++kk)
@@ -285,13 +286,71 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_reg(LarfbArgs<T> a) {
   larfb_reg_body<T, KT, IB, NW, SPW, VEC, PREC>(a, (int)(id % gridDim.x), (int)(id / gridDim.x));
 }
 
-// Split form of one tall panel (reflectors longer than a strip's registers hold):
-// row blocks of the register capacity, MODE 1 (partial Z per block) or MODE 2
-// (pass 2 with the reduced Z'), grid (strips, blocks).
-template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int MODE>
-__global__ void __launch_bounds__(NW * 64) k_larfb_split(LarfbArgs<T> a, T* zw) {
+// Split form of one tall panel (reflectors longer than a strip's registers hold).
+// First pass, grid (strips, row ranges): Z = V^T C over rows [c R1, (c + 1) R1) of
+// the strip, summed register block by register block (SPW x NW slabs of 16 rows)
+// in row order, the NW wave partials then added in fixed order; written to
+// zw[c * strips + strip].  C is only read.
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC>
+__global__ void __launch_bounds__(NW * 64) k_larfb_split_p1(LarfbArgs<T> a, T* zw) {
+  typedef typename Acc<T>::type AccT;
+  constexpr int KR = KT * 16, CB = IB * 16, R0 = SPW * NW * 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Zs = reinterpret_cast<T*>(smem_raw);  // [NW][KR][CB] wave partials
   const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.y * gridDim.x, (int64_t)gridDim.x * gridDim.y);
-  larfb_reg_body<T, KT, IB, NW, SPW, VEC, 0, MODE>(a, (int)(id % gridDim.x), (int)(id / gridDim.x), zw);
+  const int strip = (int)(id % gridDim.x), c = (int)(id / gridDim.x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, nl = lane & 15;
+  const int64_t row0 = (int64_t)c * a.chunk_rows;
+  const int Hc = (int)(c == a.P - 1 ? a.h - row0 : a.chunk_rows);
+  const int64_t colbase = a.col0 + (int64_t)strip * CB;
+  const T* V = a.V + row0;
+  AccT Z[KT][IB];
+#pragma unroll
+  for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+  for (int base = 0; base < Hc; base += R0) {
+    T cr[SPW][IB][4], vr[SPW][KT][4];
+#pragma unroll
+    for (int j = 0; j < SPW; ++j) {
+      const int q0 = base + (wv + j * NW) * 16;
+#pragma unroll
+      for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
+#pragma unroll
+      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+    }
+#pragma unroll
+    for (int j = 0; j < SPW; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[j][mt][i], cr[j][nt][i], Z[mt][nt]);
+  }
+  T* mine = Zs + (size_t)wv * KR * CB;
+#pragma unroll
+  for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < IB; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mine[(mt * 16 + acc_row<T>(g, r)) * CB + nt * 16 + nl] = Z[mt][nt][r];
+  __syncthreads();
+  T* out = zw + ((int64_t)c * gridDim.x + strip) * (KR * CB);
+  for (int e = threadIdx.x; e < KR * CB; e += NW * 64) {
+    T acc = Zs[e];
+    for (int w = 1; w < NW; ++w) acc += Zs[(size_t)w * KR * CB + e];
+    out[e] = acc;
+  }
+}
+
+// Split form, second pass, grid (strips, register blocks of R0 rows): C -= V Z'
+// with the strip's Z' from zw[strip]; LDS holds one 16-row V slab per wave.
+template <typename T, int KT, int IB, int NW, int SPW, bool VEC>
+__global__ void __launch_bounds__(NW * 64) k_larfb_split_p2(LarfbArgs<T> a, T* zw) {
+  const int64_t id = xcd_pair_id(blockIdx.x + (int64_t)blockIdx.y * gridDim.x, (int64_t)gridDim.x * gridDim.y);
+  larfb_reg_body<T, KT, IB, NW, SPW, VEC, 0, 2>(a, (int)(id % gridDim.x), (int)(id / gridDim.x), zw);
 }
 
 // Z = sum of the P blocks' partial Z in block order, then Z' = T^T Z (T the panel's
@@ -506,7 +565,7 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_stream(LarfbArgs<T> a) {
 template <typename T, int KT, int IB, int NW, bool VEC, int PREC>
 static hipError_t launch_larfb_reg(const LarfbArgs<T>& a, hipStream_t st) {
   constexpr int SPW = larfb_spw(KT * 16, NW);
-  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  constexpr size_t lds = larfb_reg_lds<T>(KT, IB, NW);
   static bool configured = false;
   if (!configured) {
     hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg<T, KT, IB, NW, SPW, VEC, PREC>,
@@ -532,7 +591,7 @@ inline bool small_update_rows(int P, int64_t h) { return P == 1 && h <= kSmallUp
 
 template <typename T, int IB, bool VEC, int PREC>
 static hipError_t launch_larfb_small(const LarfbArgs<T>& a, hipStream_t st) {
-  constexpr size_t lds = larfb_lds<T>(1, IB, 4);
+  constexpr size_t lds = larfb_reg_lds<T>(1, IB, 4);
   const int64_t ncols = a.col1 - a.col0;
   const dim3 grid((unsigned)((ncols + IB * 16 - 1) / (IB * 16)), 1);
   hipLaunchKernelGGL((k_larfb_reg<T, 1, IB, 4, 8, VEC, PREC>), grid, dim3(256), lds, st, a);
@@ -558,7 +617,7 @@ static hipError_t launch_larfb_small_ib(const LarfbArgs<T>& a, hipStream_t st) {
 
 template <typename T, int IB, bool VEC, int PREC>
 static hipError_t launch_larfb_small_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, hipStream_t st) {
-  constexpr size_t lds = larfb_lds<T>(1, IB, 4);
+  constexpr size_t lds = larfb_reg_lds<T>(1, IB, 4);
   const dim3 grid((unsigned)((max_ncols + IB * 16 - 1) / (IB * 16)), 1, (unsigned)count);
   hipLaunchKernelGGL((k_larfb_reg_b<T, 1, IB, 4, 8, VEC, PREC>), grid, dim3(256), lds, st, tab, (int64_t)0,
                      (int64_t)kSmallUpdateRows);
@@ -652,7 +711,7 @@ template <typename T, int KT, int IB, int NW, bool VEC, int PREC>
 static hipError_t launch_larfb_reg_b(const LarfbArgs<T>* tab, int count, int64_t max_ncols, int64_t h_lo,
                                      hipStream_t st) {
   constexpr int SPW = larfb_spw(KT * 16, NW);
-  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
+  constexpr size_t lds = larfb_reg_lds<T>(KT, IB, NW);
   static bool configured = false;
   if (!configured) {
     hipError_t e = hipFuncSetAttribute((const void*)k_larfb_reg_b<T, KT, IB, NW, SPW, VEC, PREC>,
@@ -715,33 +774,48 @@ static hipError_t launch_larfb_b_kt(int nw, int ib, int prec, int vec, const Lar
 }
 
 // ---- split form of one tall panel ----
+// Rows per first-pass workgroup: whole register blocks of R0 rows, enough row ranges
+// that strips x ranges reaches about 4096 workgroups, and no more, so the partial
+// sums (KR x CB per workgroup) stay a small fraction of C.
+static int64_t split_p1_rows(int64_t h, int64_t nstrips, int64_t R0) {
+  const int64_t nb = (h + R0 - 1) / R0;
+  const int64_t ranges = std::max<int64_t>(1, std::min<int64_t>(nb, (4096 + nstrips - 1) / nstrips));
+  return (nb + ranges - 1) / ranges * R0;
+}
+
 template <typename T, int KT, int IB, int NW, bool VEC>
 static hipError_t launch_larfb_split_v(const LarfbArgs<T>& a0, T* zw, hipStream_t st) {
   constexpr int SPW = larfb_spw(KT * 16, NW), KR = KT * 16, CB = IB * 16;
-  constexpr int64_t R0 = (int64_t)SPW * NW * 16;  // rows of one block (the register capacity)
-  constexpr size_t lds = larfb_lds<T>(KT, IB, NW);
-  LarfbArgs<T> a = a0;
-  a.chunk_rows = R0;
-  a.P = (int32_t)((a0.h + R0 - 1) / R0);
-  a.rm.chunk_stride = R0;  // block c holds rows c R0 .. of the single panel
-  const int64_t nstrips = (a.col1 - a.col0 + CB - 1) / CB;
+  constexpr int64_t R0 = (int64_t)SPW * NW * 16;  // rows of one register block
+  constexpr size_t lds1 = (size_t)NW * KR * CB * sizeof(T);
+  constexpr size_t lds2 = larfb_reg_lds<T>(KT, IB, NW);  // pass 2 uses the per-wave transpose slabs
+  const int64_t nstrips = (a0.col1 - a0.col0 + CB - 1) / CB;
+  LarfbArgs<T> a1 = a0, a2 = a0;
+  a1.chunk_rows = split_p1_rows(a0.h, nstrips, R0);  // first pass: row ranges of whole blocks
+  a1.P = (int32_t)((a0.h + a1.chunk_rows - 1) / a1.chunk_rows);
+  a1.rm.chunk_stride = a1.chunk_rows;
+  a2.chunk_rows = R0;  // second pass: one register block per workgroup
+  a2.P = (int32_t)((a0.h + R0 - 1) / R0);
+  a2.rm.chunk_stride = R0;
+  if (a2.P > 65535) return hipErrorInvalidValue;  // grid y limit
   T* zpart = zw;
-  T* zprime = zw + (int64_t)a.P * nstrips * KR * CB;
+  T* zprime = zw + (int64_t)a1.P * nstrips * KR * CB;
   static bool configured = false;
   if (!configured) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_split<T, KT, IB, NW, SPW, VEC, 1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_larfb_split_p1<T, KT, IB, NW, SPW, VEC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_larfb_split<T, KT, IB, NW, SPW, VEC, 2>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      e = hipFuncSetAttribute((const void*)k_larfb_split_p2<T, KT, IB, NW, SPW, VEC>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
     if (e != hipSuccess) return e;
     configured = true;
   }
-  const dim3 grid((unsigned)nstrips, (unsigned)a.P);
-  hipLaunchKernelGGL((k_larfb_split<T, KT, IB, NW, SPW, VEC, 1>), grid, dim3(NW * 64), lds, st, a, zpart);
+  hipLaunchKernelGGL((k_larfb_split_p1<T, KT, IB, NW, SPW, VEC>), dim3((unsigned)nstrips, (unsigned)a1.P),
+                     dim3(NW * 64), lds1, st, a1, zpart);
   hipLaunchKernelGGL((k_larfb_split_z<T, KT, IB>), dim3((unsigned)nstrips), dim3(256), 0, st, (const T*)zpart, zprime,
-                     (int)a.P, a.Tm, a.ldt, a.k);
-  hipLaunchKernelGGL((k_larfb_split<T, KT, IB, NW, SPW, VEC, 2>), grid, dim3(NW * 64), lds, st, a, zprime);
+                     (int)a1.P, a0.Tm, a0.ldt, a0.k);
+  hipLaunchKernelGGL((k_larfb_split_p2<T, KT, IB, NW, SPW, VEC>), dim3((unsigned)nstrips, (unsigned)a2.P),
+                     dim3(NW * 64), lds2, st, a2, zprime);
   return hipGetLastError();
 }
 template <typename T, int KT, int IB, int NW>
@@ -803,8 +877,9 @@ bool larfb_split_ok(int tile, int nw, int ib) {
 template <typename T>
 int64_t larfb_split_work(int tile, int nw, int ib, int64_t h, int64_t ncols) {
   const int64_t R0 = (int64_t)larfb_spw(tile, nw) * nw * 16;
-  const int64_t P = (h + R0 - 1) / R0, CB = 16 * ib, nstrips = (ncols + CB - 1) / CB;
-  return (P + 1) * nstrips * tile * CB;
+  const int64_t CB = 16 * ib, nstrips = (ncols + CB - 1) / CB;
+  const int64_t R1 = split_p1_rows(h, nstrips, R0), P1 = (h + R1 - 1) / R1;
+  return (P1 + 1) * nstrips * tile * CB;
 }
 
 template <typename T>
