@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-tuned", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and reduced-precision reports")
+    ap.add_argument("--paper-protocol", action="store_true",
+                    help="run only the trailing-update kernel sweep at 16384^2, tile 64, and print its report")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -228,6 +230,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.paper_protocol:
+        print("[bench] paper protocol (update kernel alone, 16384^2, tile 64)", file=sys.stderr, flush=True)
+        print(json.dumps({"paper_protocol": paper_protocol_report(torch)}))
+        return
     n, dtype = args.n, args.dtype
     print(f"[bench] generating n={n} {dtype} input", file=sys.stderr, flush=True)
     a_np = workloads.cfg1_matrix(n, dtype)

@@ -87,6 +87,13 @@ __device__ __forceinline__ double row_sum32(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Value of lane l (wave-uniform l) of v, as a wave-uniform result.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // LDS pointer types: indexing through them keeps address arithmetic in 32 bits.
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef double f64x2 __attribute__((ext_vector_type(2)));

@@ -225,13 +225,14 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
         if (q == j) alpha_l = v;
       }
       const double ss = wave_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
-      const double alpha = __shfl(alpha_l, j & 63, kWave);
+      const double alpha = lane_value(alpha_l, j & 63);
       double beta = alpha, tau = 0.0, scal = 0.0;
       if (ss > 0.0) {
         const double nrm = sqrt(alpha * alpha + ss);
         beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
+        // divisors >= sqrt(ss) >= 2^-537, normal with normal reciprocals
+        tau = nr_div(beta - alpha, beta);
+        scal = nr_div(1.0, alpha - beta);
       }
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {

@@ -97,8 +97,8 @@ __device__ void chase_task(const ChaseCtx& X, int64_t p, int64_t c, double* tile
     if (ss > 0.0) {
       const double nrm = sqrt(alpha * alpha + ss);
       beta = alpha >= 0.0 ? -nrm : nrm;
-      scal = 1.0 / (alpha - beta);
-      tau = (beta - alpha) / beta;
+      scal = nr_div(1.0, alpha - beta);  // divisors >= sqrt(ss), normal whenever ss > 0
+      tau = nr_div(beta - alpha, beta);
     }
   }
   for (int half = 0; half * 64 < L; ++half) {
@@ -152,8 +152,8 @@ __device__ void chase_task(const ChaseCtx& X, int64_t p, int64_t c, double* tile
     if (ss > 0.0) {
       const double nrm = sqrt(alpha * alpha + ss);
       beta = alpha >= 0.0 ? -nrm : nrm;
-      scal = 1.0 / (alpha - beta);
-      tau = (beta - alpha) / beta;
+      scal = nr_div(1.0, alpha - beta);  // divisors >= sqrt(ss), normal whenever ss > 0
+      tau = nr_div(beta - alpha, beta);
     }
   }
   for (int half = 0; half * 64 < L; ++half) {
@@ -337,13 +337,6 @@ __device__ __forceinline__ int ring_slot(int64_t r, int64_t base, int R) {
   return (int)((uint32_t)(r - base) % (uint32_t)R);
 }
 
-// Value of lane l of v (a wave-uniform result).
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
 // Householder reflector H = I - tau v v^T with H x = beta e_1, for the vector x
 // held one entry per lane (lanes >= L hold 0).  v is returned per lane (v_0 = 1,
 // zero beyond L); x = 0 below its first entry gives tau = 0 (H = I).
@@ -358,8 +351,8 @@ __device__ __forceinline__ void wave_reflector(double x, int lane, int L, double
   if (ss > 0.0) {
     const double nrm = sqrt(alpha * alpha + ss);
     beta = alpha >= 0.0 ? -nrm : nrm;
-    scal = 1.0 / (alpha - beta);
-    tau = (beta - alpha) / beta;
+    scal = nr_div(1.0, alpha - beta);  // divisors >= sqrt(ss), normal whenever ss > 0
+    tau = nr_div(beta - alpha, beta);
   }
   v = lane < L ? (lane == 0 ? 1.0 : x * scal) : 0.0;
 }
