@@ -46,6 +46,8 @@ struct LarfbArgs {
   int32_t vec;        // 1: view rows contiguous in memory and every 4-row group of C and V
                       // 16-byte aligned (float only), so 4 rows load as one access
   int32_t prec;       // MFMA operand precision: 0 = T, 2 = BF16, 3 = FP16 (float only)
+  int32_t vecv = 0;   // 1: V alone allows 16-byte loads of 4 rows (float only; C may not,
+                      // as in the LQ sweep, whose view rows are memory columns)
 };
 
 // Slabs (16 rows) per wave of the trailing update: enough for the largest chunk a

@@ -172,6 +172,12 @@ int larfb_vec_ok(const LarfbArgs<T>& a) {
   const bool v4 = (reinterpret_cast<uintptr_t>(a.V) % 16) == 0 && a.ldv % 4 == 0 && a.chunk_rows % 4 == 0;
   return rows4 && mat4 && v4 ? 1 : 0;
 }
+// V alone: 16-byte loads of 4 consecutive reflector rows (float only).
+template <typename T>
+int larfb_vecv_ok(const LarfbArgs<T>& a) {
+  if (sizeof(T) != 4) return 0;
+  return (reinterpret_cast<uintptr_t>(a.V) % 16) == 0 && a.ldv % 4 == 0 && a.chunk_rows % 4 == 0 ? 1 : 0;
+}
 
 std::vector<Level> plan_panel(int64_t r0, int64_t h, int bw, int tile, int hmax) {
   std::vector<Level> L;
@@ -353,6 +359,7 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
       a.ldt = cfg.tile;
       a.k = (int32_t)(lv.P == 1 ? std::min<int64_t>(bw, lv.h) : bw);
       a.vec = larfb_vec_ok(a);
+      a.vecv = larfb_vecv_ok(a);
       a.prec = cfg.update_precision;
       g_timing.kbegin(0, st);
       HIPCHK(launch_larfb<T>(cfg.tile, cfg.threads / 64, cfg.inner_block, a, st));
@@ -618,6 +625,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         u.k = (int32_t)std::min<int64_t>(bw, h);
         u.prec = cfg.update_precision;
         u.vec = larfb_vec_ok(u);
+        u.vecv = larfb_vecv_ok(u);
         vec_qr[k] &= u.vec;
         mc_qr[k] = std::max<int64_t>(mc_qr[k], u.col1 - u.col0);
         if (u.col1 > u.col0) {
@@ -655,6 +663,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         u.k = (int32_t)std::min<int64_t>(b, h);
         u.prec = cfg.update_precision;
         u.vec = larfb_vec_ok(u);
+        u.vecv = larfb_vecv_ok(u);
         vec_lq[k] &= u.vec;
         mc_lq[k] = std::max<int64_t>(mc_lq[k], u.col1 - u.col0);
         if (u.col1 > u.col0) {
@@ -987,6 +996,7 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
     a.ldt = ldt;
     a.k = (int32_t)k;
     a.vec = larfb_vec_ok(a);
+      a.vecv = larfb_vecv_ok(a);
     a.prec = c.update_precision;
     if (split) {
       const int64_t elems = larfb_split_work<T>(c.tile, c.threads / 64, c.inner_block, vrows, a.col1 - a.col0);

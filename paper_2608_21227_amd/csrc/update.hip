@@ -77,9 +77,9 @@ __device__ __forceinline__ void store_c(const LarfbArgs<T>& a, int c, int Hc, in
 template <typename T, bool VEC>
 __device__ __forceinline__ void load_v1(const LarfbArgs<T>& a, const T* V, int Hc, int q0, int g, int r, T (&x)[4]) {
   const bool rok = r < a.k;
-  if constexpr (VEC) {
+  if constexpr (sizeof(T) == 4) {
     const int qa = q0 + 4 * g;
-    if (rok && qa + 3 < Hc) {
+    if ((VEC || a.vecv) && rok && qa + 3 < Hc) {
       const float4 v = *reinterpret_cast<const float4*>(V + qa + (int64_t)r * a.ldv);
       x[0] = v.x;
       x[1] = v.y;
