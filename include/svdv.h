@@ -155,11 +155,13 @@ int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_d
  *   C  h x w, column-major, leading dimension ldc, updated in place.
  *   k  <= cfg->tile.  All three in `dtype`.
  *   A reflector length (h for side 0, w for side 1) above 32768 / cfg->tile (the
- *   rows one workgroup can hold in registers) runs split over row blocks of that
- *   size (partial V^T C per block in the library's workspace, one reduction with
- *   T, then the update per block) when the configuration has a register strip,
- *   else the streaming form of the kernel; a configuration with neither returns
- *   SVDV_ERR_UNSUPPORTED.  Tall panels take float32/float64 updates only.
+ *   rows one workgroup can hold in registers) runs the split form when the
+ *   configuration has a register strip: partial V^T C over row ranges into the
+ *   library's workspace, their sum in a fixed order with T^T applied, then
+ *   C - V Z' per block of 32768 / cfg->tile rows (bitwise reproducible from call
+ *   to call); else the streaming form of the kernel; a configuration with
+ *   neither returns SVDV_ERR_UNSUPPORTED.  Tall panels take float32/float64
+ *   updates only.
  */
 int svdv_apply_qt(const void* V, int64_t ldv, const void* T, int64_t ldt, void* C, int64_t ldc, int64_t h, int64_t w,
                   int64_t k, int32_t dtype, int32_t side, void* stream, const svdv_config* cfg);
