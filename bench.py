@@ -174,7 +174,9 @@ def paper_protocol_report(torch, n: int = 16384, tile: int = 64, reps: int = 5):
     configuration times and their ratio, beside the paper's Table 2."""
     g = torch.Generator(device="cuda").manual_seed(260821227)
     C = torch.randn(n, n, device="cuda", dtype=torch.float32, generator=g).t()  # column-major view
-    V = torch.randn(tile, n, device="cuda", dtype=torch.float32, generator=g).t()
+    # reflector entries of size 1/sqrt(n) (as a Householder vector's are): the ~70
+    # launches of the sweep, all on the same C, keep its values finite
+    V = torch.randn(tile, n, device="cuda", dtype=torch.float32, generator=g).t() / np.sqrt(n)
     V = torch.tril(V, -1) + torch.eye(n, tile, device="cuda", dtype=torch.float32)
     V = V.t().contiguous().t()  # unit lower trapezoidal, column-major
     Tm = (torch.triu(torch.randn(tile, tile, device="cuda", dtype=torch.float32, generator=g)) * 0.01).t().contiguous().t()

@@ -35,6 +35,27 @@ def test_apply_qt_tall_split(side, vr, other, k, tile, threads, ib):
     _apply_qt_case("float32", side, h, w, k, tile, threads, ib)
 
 
+def test_apply_qt_tall_split_is_reproducible():
+    torch = torch_cuda()
+    svdv = _svdv()
+    cfg = svdv.Config(tile=64, threads=512, inner_block=2, sweep_width=1)
+    rng = np.random.default_rng(5)
+    h, w, k = 3000, 200, 64
+    V = np.tril(rng.standard_normal((h, k)), -1) / np.sqrt(h)
+    V[np.arange(k), np.arange(k)] = 1.0
+    T = np.triu(rng.standard_normal((k, k)) * 0.3)
+    C = rng.standard_normal((h, w))
+    banner(f"apply_qt split reproducible h={h} w={w} k={k}")
+    Vd, Td = (to_dev(x.astype(np.float32), torch, fortran=True) for x in (V, T))
+    outs = []
+    for _ in range(2):
+        Cd = to_dev(C.astype(np.float32), torch, fortran=True)
+        svdv.apply_qt(Vd, Td, Cd, side=0, config=cfg)
+        torch.cuda.synchronize()
+        outs.append(Cd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])  # fixed-order reductions, no atomics
+
+
 def _apply_qt_case(dtype, side, h, w, k, tile, threads, ib):
     torch = torch_cuda()
     svdv = _svdv()
