@@ -35,6 +35,29 @@ def test_apply_qt_tall_split(side, vr, other, k, tile, threads, ib):
     _apply_qt_case("float32", side, h, w, k, tile, threads, ib)
 
 
+# first-pass workgroups summing several register blocks (3 per row range here, a
+# ragged last range), with two blocks in flight (inner_block 1) or one (inner_block 2)
+@pytest.mark.parametrize("ib", [1, 2])
+def test_apply_qt_split_multi_block(ib):
+    torch = torch_cuda()
+    svdv = _svdv()
+    cfg = svdv.Config(tile=64, threads=512, inner_block=ib, sweep_width=1)
+    rng = np.random.default_rng(40000 + ib)
+    h, w, k = 40000, 2048, 64
+    V = (np.tril(rng.standard_normal((h, k)), -1) / np.sqrt(h)).astype(np.float32)
+    V[np.arange(k), np.arange(k)] = 1.0
+    T = np.triu(rng.standard_normal((k, k)) * 0.3).astype(np.float32)
+    C = rng.standard_normal((h, w)).astype(np.float32)
+    V64 = V.astype(np.float64)
+    want = C.astype(np.float64) - V64 @ (T.astype(np.float64).T @ (V64.T @ C.astype(np.float64)))
+    banner(f"apply_qt split multi-block h={h} w={w} k={k} ib={ib}")
+    Vd, Td, Cd = (to_dev(x, torch, fortran=True) for x in (V, T, C))
+    svdv.apply_qt(Vd, Td, Cd, side=0, config=cfg)
+    torch.cuda.synchronize()
+    got = Cd.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) <= 2e-6 * (np.abs(want).max() + np.abs(C).max()) * np.sqrt(k)
+
+
 def test_apply_qt_tall_split_is_reproducible():
     torch = torch_cuda()
     svdv = _svdv()
