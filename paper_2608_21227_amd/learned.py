@@ -7,7 +7,7 @@ which needs every configuration measured.  Here a small perceptron (6 -> 64 ->
 library's GPU kernels (forward, gradient, Adam: ``mlp_*`` in the package),
 predicts log run time from six features of (n, dtype, configuration).  For a
 new (n, dtype) cell the valid configurations are ranked by prediction and the
-best k are measured; exhaustive search stays the judge: the regret of a
+best k are measured; exhaustive search stays the reference: the regret of a
 budget-k search is min(measured time of the k chosen) / (exhaustive best) - 1,
 and random search with the same budget is the baseline it must beat.
 """
