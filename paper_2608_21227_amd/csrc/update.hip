@@ -103,6 +103,10 @@ template <typename T, int KT, int IB, int NW, int SPW, bool VEC, int PREC, int M
 __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int strip, const int c, T* zw = nullptr) {
   typedef typename Acc<T>::type AccT;
   constexpr int KR = KT * 16, CB = IB * 16;
+  // MODE 2 with strips of 32 or more columns loads each slab's V just before its
+  // transpose rather than with the strip: fewer registers live, more workgroups per
+  // CU (with 16-column strips the early loads measured faster)
+  constexpr bool kLateV = MODE == 2 && IB >= 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // [NW][KR][CB] partial sums (slot 0 then holds Z); in pass 2 the same space holds
   // each wave's [16][KR + 4] V slab being transposed
@@ -128,8 +132,10 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
     if (s < nslab) {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
+      if constexpr (!kLateV) {
 #pragma unroll
-      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+        for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+      }
     } else {
 #pragma unroll
       for (int nt = 0; nt < IB; ++nt)
@@ -235,6 +241,10 @@ __device__ __forceinline__ void larfb_reg_body(const LarfbArgs<T>& a, const int 
       // va[j][kk] needs row nl, reflector r(kk, g).  The Zs space is free here (Z'
       // was formed behind a barrier) and each wave touches only its own slab.
       T* buf = Zs + (size_t)wv * 16 * (KR + 4);
+      if constexpr (kLateV) {
+#pragma unroll
+        for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, s * 16, g, mt * 16 + nl, vr[j][mt]);
+      }
 #pragma unroll
       for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
