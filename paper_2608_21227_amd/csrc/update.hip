@@ -320,24 +320,30 @@ __global__ void __launch_bounds__(NW * 64) k_larfb_split_p1(LarfbArgs<T> a, T* z
   for (int mt = 0; mt < KT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = AccT{0, 0, 0, 0};
+  // with strips of 32 or more columns a block's slabs are taken in two halves (the
+  // same slab order, so the same sums): half the registers live, more workgroups per CU
+  constexpr int SH = (IB >= 2 && SPW % 2 == 0) ? SPW / 2 : SPW;
   for (int base = 0; base < Hc; base += R0) {
-    T cr[SPW][IB][4], vr[SPW][KT][4];
 #pragma unroll
-    for (int j = 0; j < SPW; ++j) {
-      const int q0 = base + (wv + j * NW) * 16;
+    for (int j0 = 0; j0 < SPW; j0 += SH) {
+      T cr[SH][IB][4], vr[SH][KT][4];
 #pragma unroll
-      for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[j][nt]);
+      for (int jj = 0; jj < SH; ++jj) {
+        const int q0 = base + (wv + (j0 + jj) * NW) * 16;
 #pragma unroll
-      for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[j][mt]);
+        for (int nt = 0; nt < IB; ++nt) load_c<T, VEC>(a, c, Hc, q0, g, colbase + nt * 16 + nl, cr[jj][nt]);
+#pragma unroll
+        for (int mt = 0; mt < KT; ++mt) load_v1<T, VEC>(a, V, Hc, q0, g, mt * 16 + nl, vr[jj][mt]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < SH; ++jj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int mt = 0; mt < KT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[jj][mt][i], cr[jj][nt][i], Z[mt][nt]);
     }
-#pragma unroll
-    for (int j = 0; j < SPW; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int mt = 0; mt < KT; ++mt)
-#pragma unroll
-          for (int nt = 0; nt < IB; ++nt) Z[mt][nt] = mfma16(vr[j][mt][i], cr[j][nt][i], Z[mt][nt]);
   }
   T* mine = Zs + (size_t)wv * KR * CB;
 #pragma unroll
