@@ -226,7 +226,7 @@ def main():
                     help="run only the trailing-update kernel sweep at 16384^2, tile 64, and print its report")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 (the split over several GPUs is a design, not implemented)"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
