@@ -264,6 +264,15 @@ def main():
         ref = np.load(gold)
         diff = np.abs(s_tuned - ref)
         parity = {"normwise": float(diff.max() / ref[0]), "max_rel": float(np.max(diff / ref))}
+        # the parity gate of the tests: float64 normwise <= 1e-12; float32 normwise <= 1e-5
+        # and per-value relative <= 1e-5 * cond (cond of the oracle's values)
+        if dtype == "float64":
+            parity["gate"] = "normwise <= 1e-12"
+            parity["pass"] = parity["normwise"] <= 1e-12
+        else:
+            cond = float(ref[0] / ref[-1])
+            parity["gate"] = f"normwise <= 1e-5 and max_rel <= 1e-5 * cond ({cond:.4g})"
+            parity["pass"] = parity["normwise"] <= 1e-5 and parity["max_rel"] <= 1e-5 * cond
 
     # roofline of each hot kernel class, measured live (events on the library's stream)
     b = tuned.tile
@@ -339,6 +348,9 @@ def main():
         print("[bench] paper protocol (update kernel alone, 16384^2, tile 64)", file=sys.stderr, flush=True)
         out["paper_protocol"] = paper_protocol_report(torch)
     print(json.dumps(out))
+    if parity is not None and not parity["pass"]:
+        print(f"[bench] parity gate failed: {parity}", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

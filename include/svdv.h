@@ -131,6 +131,8 @@ int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dt
  * d[0..n-1] (diagonal) and e[0..n-2] (superdiagonal), float64.  Signs of d, e
  * are not normalised.  cfg->sweep_width selects the schedule; the result is
  * bitwise identical for every sweep_width.  b must be one of the tile sizes.
+ * If a bounded wait between the chase's workgroups gives up (it never does in
+ * a correct launch), every entry of d and e is NaN after the stream completes.
  */
 int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, double* d, double* e, void* stream,
                       const svdv_config* cfg);

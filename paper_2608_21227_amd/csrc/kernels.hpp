@@ -119,6 +119,7 @@ struct BatchMat {
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n);
 __global__ void k_fill_i32(int* p, int v, int64_t n);
 __global__ void k_fill_f64(double* p, double v, int64_t n);
+__global__ void k_nan_if_flag(const int* flag, double* d, double* e, int64_t n);
 
 template <typename T>
 hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int transpose, T* W, int64_t ldw,
@@ -199,9 +200,9 @@ template <typename T>
 hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, double* work, const int* exp_in,
                          int lanes_per_value, hipStream_t st, const int* fail_flag = nullptr);
 // Batched: value v (0 <= v < total) of the flattened batch is value v - voff[vmat[v]] of matrix vmat[v];
-// max_n is the largest N of the batch.
+// max_n is the largest N of the batch; fail_flag as above, for the whole batch.
 template <typename T>
 hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
-                                 int64_t max_n, hipStream_t st);
+                                 int64_t max_n, hipStream_t st, const int* fail_flag);
 
 }  // namespace svdv

@@ -47,6 +47,16 @@ __global__ void k_fill_i32(int* p, int v, int64_t n) {
 __global__ void k_fill_f64(double* p, double v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
+// d[0 .. n) and e[0 .. n-1) become NaN when *flag is nonzero (the chase that was to
+// write them gave up a bounded wait), so no caller reads them as valid.
+__global__ void k_nan_if_flag(const int* flag, double* d, double* e, int64_t n) {
+  if (*flag == 0) return;
+  const double q = __builtin_nan("");
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    d[i] = q;
+    if (i + 1 < n) e[i] = q;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // a1: input staging -- max |a|, then copy (optionally transposed) scaled by 2^-e

@@ -215,15 +215,22 @@ __global__ void __launch_bounds__(256) k_bisect(const double* __restrict__ work,
 
 // Batched form: value v of the flattened batch belongs to matrix vmat[v] as its
 // value v - voff[vmat[v]].
+// When fail_flag holds a nonzero value (a bounded wait of the batch's chase gave
+// up) every output value of the batch is NaN.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bisect_b(const BatchMat<T>* __restrict__ tab, const int* __restrict__ vmat,
-                                                  const int64_t* __restrict__ voff, int64_t total, int lps) {
+                                                  const int64_t* __restrict__ voff, int64_t total, int lps,
+                                                  const int* fail_flag) {
   const int lane = threadIdx.x & 63;
   const int teams_per_wave = 64 / lps;
   const int64_t v = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * teams_per_wave + lane / lps;
   const bool active = v < total;
   const int mi = active ? vmat[v] : 0;
   const BatchMat<T>& t = tab[mi];
+  if (fail_flag != nullptr && *fail_flag != 0) {
+    if (active && lane % lps == 0) t.S[t.N - 1 - (v - voff[mi])] = (T)__builtin_nan("");
+    return;
+  }
   bisect_team(t.work, t.N, t.S, t.exp, active ? v - voff[mi] : 0, active, lps);
 }
 
@@ -252,7 +259,7 @@ hipError_t launch_bisect(const double* d, const double* e, int64_t n, T* S, doub
 
 template <typename T>
 hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* vmat, const int64_t* voff, int64_t total,
-                                 int64_t max_n, hipStream_t st) {
+                                 int64_t max_n, hipStream_t st, const int* fail_flag) {
   if (count <= 0 || total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bisect_prep_b<T>, dim3(count), dim3(256), 0, st, tab);
   const int64_t G = bisect_grid_points(max_n);
@@ -260,13 +267,14 @@ hipError_t launch_bisect_batched(const BatchMat<T>* tab, int count, const int* v
   const int lps = bisect_lps(total);
   const int teams_per_block = 256 / lps;
   const int64_t blocks = (total + teams_per_block - 1) / teams_per_block;
-  hipLaunchKernelGGL(k_bisect_b<T>, dim3((unsigned)blocks), dim3(256), 0, st, tab, vmat, voff, total, lps);
+  hipLaunchKernelGGL(k_bisect_b<T>, dim3((unsigned)blocks), dim3(256), 0, st, tab, vmat, voff, total, lps,
+                     fail_flag);
   return hipGetLastError();
 }
 template hipError_t launch_bisect_batched<float>(const BatchMat<float>*, int, const int*, const int64_t*, int64_t, int64_t,
-                                                 hipStream_t);
+                                                 hipStream_t, const int*);
 template hipError_t launch_bisect_batched<double>(const BatchMat<double>*, int, const int*, const int64_t*, int64_t,
-                                                  int64_t, hipStream_t);
+                                                  int64_t, hipStream_t, const int*);
 template hipError_t launch_bisect<float>(const double*, const double*, int64_t, float*, double*, const int*, int,
                                          hipStream_t, const int*);
 template hipError_t launch_bisect<double>(const double*, const double*, int64_t, double*, double*, const int*, int,

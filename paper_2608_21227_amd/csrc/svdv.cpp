@@ -277,15 +277,7 @@ int get_workspace(void* stream, size_t bytes, char** out) {
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 // Persistent grid of the bulge chase: every workgroup must be resident at once.
-// SVDV_CHASE_GRID (debugging aid) caps it further, e.g. 1 = all groups in one workgroup.
-int chase_grid(int ngroups, int b, int W) {
-  int g = std::min<int>(ngroups, chase_max_groups_resident(b, W));
-  if (const char* env = getenv("SVDV_CHASE_GRID")) {
-    const int cap = atoi(env);
-    if (cap > 0) g = std::min(g, cap);
-  }
-  return g;
-}
+int chase_grid(int ngroups, int b, int W) { return std::min<int>(ngroups, chase_max_groups_resident(b, W)); }
 
 struct Layout {
   size_t W, V, T, Bs, progress, err, amax, exp, d, e, work, total;
@@ -754,7 +746,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
     HIPCHK(launch_band_pack_batched<T>(dmats, cnt, b, maxN, st));
     HIPCHK(launch_chase_batched(L, grid, cnt, maxN, progress, nprog + 2, st));
     HIPCHK(launch_bisect_batched<T>(dmats, cnt, (const int*)(base + vmat_off), (const int64_t*)(base + voff_off),
-                                    total_vals, maxN, st));
+                                    total_vals, maxN, st, err));
     return SVDV_OK;
   };
   return SVDV_OK;
@@ -923,14 +915,14 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   ca.err = (int*)(ws + L.err);
   ca.d = d;
   ca.e = e ? e : (double*)(ws + L.e);
-  if (const char* env = getenv("SVDV_CHASE_GROUPS")) {  // debugging aid: run only the first groups
-    const int cap = atoi(env);
-    if (cap > 0 && cap < ca.ngroups) ca.ngroups = cap;
-  }
   int grid = chase_grid(ca.ngroups, (int)b, c.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
   HIPCHK(launch_chase(ca, grid, st));
+  // a bounded wait that gave up leaves the chase unfinished: d and e become NaN
+  hipLaunchKernelGGL(k_nan_if_flag, dim3(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256))), dim3(256), 0,
+                     st, ca.err, d, e, n);
+  HIPCHK(hipGetLastError());
   return SVDV_OK;
 }
 
@@ -1144,37 +1136,3 @@ int svdv_release(void) {
 }
 
 }  // extern "C"
-
-// Debugging aid (not part of the public header): run the bulge chase on a band
-// and copy the whole chase storage (n x 3b, row-major) to Bs_out (device).
-extern "C" int svdv_debug_chase(const double* band, int64_t n, int64_t b, int64_t ldband, double* Bs_out, int W,
-                                int ngroups_cap, int grid_cap) {
-  svdv_config c = default_config(n, n, SVDV_F64);
-  c.tile = (int32_t)b;
-  c.sweep_width = W;
-  hipStream_t st = nullptr;
-  Layout L = make_layout(n, n, 8, (int)b, 256, W, n);
-  char* ws = nullptr;
-  int rc = get_workspace(st, L.total, &ws);
-  if (rc) return rc;
-  double* Bs = (double*)(ws + L.Bs);
-  HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
-  ChaseArgs ca{};
-  ca.Bs = Bs;
-  ca.ldb = 3 * b;
-  ca.n = n;
-  ca.b = (int32_t)b;
-  ca.W = W;
-  ca.ngroups = (int32_t)std::max<int64_t>(1, (n - 1 + W - 1) / W);
-  if (ngroups_cap > 0 && ngroups_cap < ca.ngroups) ca.ngroups = ngroups_cap;
-  ca.progress = (int*)(ws + L.progress);
-  ca.err = (int*)(ws + L.err);
-  ca.d = (double*)(ws + L.d);
-  ca.e = (double*)(ws + L.e);
-  int grid = chase_grid(ca.ngroups, (int)b, W);
-  if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
-  HIPCHK(launch_chase(ca, grid, st));
-  HIPCHK(hipMemcpyAsync(Bs_out, Bs, (size_t)n * 3 * b * 8, hipMemcpyDeviceToDevice, st));
-  return SVDV_OK;
-}

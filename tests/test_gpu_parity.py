@@ -160,17 +160,21 @@ def test_stage_bidiag_matches_oracle(n, b):
     d_ref, e_ref = oracle.bulge_chase(band_dense, b)
     scale = np.linalg.norm(band_dense)
     results = []
-    for W in (1, 3, 8):
+    for W in (1, 2, 3, 8):
+        # the chase alone needs only its own LDS to fit for (b, W): the library
+        # reports any other width as unsupported, which skips that width
         cfg = svdv.Config(tile=b, sweep_width=W)
-        if not svdv.check_config(n, n, "float32", cfg):
-            continue
         banner(f"stage_bidiag n={n} b={b} W={W}")
-        d, e = svdv.stage_bidiag(to_dev(band, torch), b, config=cfg)
+        try:
+            d, e = svdv.stage_bidiag(to_dev(band, torch), b, config=cfg)
+        except svdv.Unsupported:
+            continue
         torch.cuda.synchronize()
         d, e = d.cpu().numpy(), e.cpu().numpy()
         assert np.max(np.abs(np.abs(d) - np.abs(d_ref))) <= 1e-12 * scale
         assert np.max(np.abs(np.abs(e) - np.abs(e_ref))) <= 1e-12 * scale
         results.append((d, e))
+    assert len(results) >= 2, f"fewer than two sweep widths ran for b={b}"
     for d, e in results[1:]:  # schedule-independent: bitwise equal for every sweep width
         assert np.array_equal(d, results[0][0]) and np.array_equal(e, results[0][1])
 
