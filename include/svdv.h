@@ -91,6 +91,27 @@ int svd_values_ex(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtyp
                   const svdv_config* cfg);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): svd_values_ex on a
+ * fixed device array of SVDV_NOALLOC_SCRATCH_BYTES bytes that the library holds
+ * on every GPU it runs on, from its load until the process ends, instead of the
+ * allocated workspace.  Same arguments, kernels and results as svd_values_ex
+ * (bitwise, for the same cfg).  This call allocates nothing: no hipMalloc or
+ * hipFree, and no per-stage timing events (svdv_timing is ignored for it).
+ * A call whose workspace exceeds the array (for example n above about 2048 in
+ * float64 or about 2900 in float32 at tile 16) returns SVDV_ERR_UNSUPPORTED
+ * before any GPU work.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (each call clears what must start at zero):
+ * calls that overlap in time on one GPU (different streams, or host threads)
+ * race and must be serialised by the caller.
+ */
+#define SVDV_NOALLOC_SCRATCH_BYTES (64 << 20)
+int svd_values_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream,
+                       const svdv_config* cfg);
+/* Size in bytes of the fixed array svd_values_noalloc works in. */
+int64_t svdv_noalloc_capacity(void);
+
+/*
  * Batched singular values of `batch` independent matrices of uneven sizes.
  *   A_array   HOST array [batch] of device pointers to column-major matrices.
  *   m, n, lda HOST arrays [batch].

@@ -20,8 +20,8 @@ STATUS = {0: "SVDV_OK", -1: "SVDV_ERR_INVALID_ARG", -2: "SVDV_ERR_UNSUPPORTED", 
           -4: "SVDV_ERR_HIP"}
 
 # Every symbol include/svdv.h declares (checked by the CPU test-suite).
-EXPORTS = ["svd_values", "svd_values_ex", "svd_values_batched", "svdv_default_config", "svdv_check_config",
-           "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
+EXPORTS = ["svd_values", "svd_values_ex", "svd_values_noalloc", "svdv_noalloc_capacity", "svd_values_batched",
+           "svdv_default_config", "svdv_check_config", "svdv_stage_band", "svdv_stage_bidiag", "svdv_stage_values", "svdv_apply_qt", "svdv_status_string",
            "svdv_last_error", "svdv_release", "svdv_timing", "svdv_last_timing",
            "svdv_last_kernel_stats", "svdv_mlp_work_size", "svdv_mlp_forward", "svdv_mlp_gradient",
            "svdv_mlp_adam_step"]
@@ -72,6 +72,7 @@ def lib():
         sig = {
             "svd_values": [vp, i64, i64, i64, i32, vp, vp],
             "svd_values_ex": [vp, i64, i64, i64, i32, vp, vp, cfgp],
+            "svd_values_noalloc": [vp, i64, i64, i64, i32, vp, vp, cfgp],
             "svd_values_batched": [vp, vp, vp, vp, i64, i32, vp, vp, vp, cfgp],
             "svdv_default_config": [i64, i64, i32, cfgp],
             "svdv_check_config": [i64, i64, i32, cfgp],
@@ -92,6 +93,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.svdv_noalloc_capacity.argtypes = []
+        L.svdv_noalloc_capacity.restype = i64
         L.svdv_mlp_work_size.argtypes = [i64]
         L.svdv_mlp_work_size.restype = i64
         L.svdv_status_string.argtypes = [ctypes.c_int]
@@ -174,6 +177,21 @@ def svd_values(a, config=None, out=None):
     _check(lib().svd_values_ex(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(s.data_ptr()),
                                _stream(a.device), _cfg_ptr(config)))
     return s
+
+
+def svd_values_noalloc(a, out, config=None):
+    """svd_values through the allocation-free entry point: the library works in its
+    fixed device array (no device allocation); ``out`` (min(m, n) values, a's dtype)
+    is supplied by the caller."""
+    if a.dim() != 2 or not a.is_cuda:
+        raise ValueError("expected a 2-D tensor on a GPU")
+    dt = _dtype_code(a)
+    a2, m, n, lda = _as_colmajor(a)
+    if out.numel() < min(m, n) or out.dtype != a.dtype:
+        raise ValueError("out is too small or of the wrong dtype")
+    _check(lib().svd_values_noalloc(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(out.data_ptr()),
+                                    _stream(a.device), _cfg_ptr(config)))
+    return out
 
 
 def svd_values_batched(mats, config=None, out=None):

@@ -397,17 +397,28 @@ int check_matrix_args(const void* A, int64_t m, int64_t n, int64_t lda, int dtyp
   return SVDV_OK;
 }
 
+// ext_ws (optional): a caller-provided workspace of ext_bytes bytes used instead of
+// the cached allocation; a layout larger than it is rejected before any GPU work.
 template <typename T>
 int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_t st, const svdv_config& cfg,
-                 double* band_out, int64_t ldband, double* d_out, double* e_out) {
+                 double* band_out, int64_t ldband, double* d_out, double* e_out, char* ext_ws = nullptr,
+                 size_t ext_bytes = 0) {
   const int transpose = m < n;
   const int64_t M = transpose ? n : m, N = transpose ? m : n;
   const int64_t ldw = (M + 15) / 16 * 16;
   const int hmax = chunk_qr_hmax<T>(cfg.tile);
   Layout L = make_layout(M, N, sizeof(T), cfg.tile, hmax, cfg.sweep_width, ldw);
   char* ws = nullptr;
-  int rc = get_workspace(st, L.total, &ws);
-  if (rc) return rc;
+  int rc = SVDV_OK;
+  if (ext_ws) {
+    if (L.total > ext_bytes)
+      return fail(SVDV_ERR_UNSUPPORTED, "workspace of " + std::to_string(L.total) + " bytes exceeds the fixed array of " +
+                                            std::to_string(ext_bytes) + " bytes");
+    ws = ext_ws;
+  } else {
+    rc = get_workspace(st, L.total, &ws);
+    if (rc) return rc;
+  }
   T* W = (T*)(ws + L.W);
   T* vws = (T*)(ws + L.V);
   T* tws = (T*)(ws + L.T);
@@ -454,6 +465,33 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   if (S) HIPCHK(launch_bisect<T>(d, e, N, S, work, expo, 0, st, err));
   g_timing.mark(5, st);
   g_timing.valid = g_timing.enabled;
+  return SVDV_OK;
+}
+
+// ----------------------------------------------------------------------------
+// fixed device array of the allocation-free entry point
+// ----------------------------------------------------------------------------
+// Each GPU the library runs on holds its own copy of `scratch` from the module's
+// load until the process ends.  In host code the name is only a stand-in for the
+// symbol: the device address of a GPU's copy comes from hipGetSymbolAddress with
+// that GPU current, looked up once per device and kept here.
+constexpr size_t kNoallocBytes = (size_t)SVDV_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kNoallocBytes];
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+int scratch_address(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    it = g_scratch_ptr.emplace(dev, (char*)p).first;
+  }
+  *out = it->second;
   return SVDV_OK;
 }
 
@@ -867,6 +905,35 @@ int svd_values_ex(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtyp
 int svd_values(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream) {
   return svd_values_ex(A, m, n, lda, dtype, S, stream, nullptr);
 }
+
+int svd_values_noalloc(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream,
+                       const svdv_config* cfg) {
+  int rc = check_matrix_args(A, m, n, lda, dtype);
+  if (rc) return rc;
+  const int64_t k = std::min(m, n);
+  if (k == 0) return SVDV_OK;
+  if (!S) return fail(SVDV_ERR_INVALID_ARG, "S is NULL");
+  svdv_config c = cfg ? *cfg : default_config(m, n, dtype);
+  rc = check_config_impl(m, n, dtype, c);
+  if (rc) return rc;
+  char* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // no event creation on this path: per-stage timing is left off for the call
+  const bool timing = g_timing.enabled;
+  g_timing.enabled = false;
+  if (dtype == SVDV_F32)
+    rc = svd_values_t<float>((const float*)A, m, n, lda, (float*)S, st, c, nullptr, 0, nullptr, nullptr, ws,
+                             kNoallocBytes);
+  else
+    rc = svd_values_t<double>((const double*)A, m, n, lda, (double*)S, st, c, nullptr, 0, nullptr, nullptr, ws,
+                              kNoallocBytes);
+  g_timing.enabled = timing;
+  return rc;
+}
+
+int64_t svdv_noalloc_capacity(void) { return (int64_t)kNoallocBytes; }
 
 int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, double* band, int64_t ldband,
                     void* stream, const svdv_config* cfg) {
