@@ -8,22 +8,23 @@
 //   applied to columns c..c+L+b-1 (this creates fill beyond the band);
 // with p_0 = s, c_0 = s+1, then p <- c, c <- c+b, and L = min(b, n-c).
 //
-// Dependencies: task j of sweep s+1 overlaps tasks j, j+1, j+2 of sweep s (the
-// last by one element), so it may start once sweep s has finished task j+2.
-// Tasks of different sweeps that respect this lag touch disjoint data, so any
-// schedule obeying it gives bitwise the same result.
+// Dependencies: task j of sweep s+1 overlaps tasks j and j+1 of sweep s in
+// whole rows and columns, and task j+2 in a single element; tasks further apart
+// are disjoint.  So a sweep may start task j once its predecessor has finished
+// task j+1 (and written the one element task j+2 shares with it), and any
+// schedule obeying that gives bitwise the same result.
 //
-// Schedule: sweeps are cut into groups of W consecutive sweeps; one workgroup
-// (W waves) owns a group and advances its sweeps in lockstep -- at step t the
-// wave of sweep s0+i runs task t-3i -- with a workgroup barrier between steps.
-// A persistent grid takes groups in increasing order from a ticket counter, so
-// the predecessor of every group being worked on is held by a workgroup that is
-// already running: no schedule can wait on a workgroup that was never made
-// resident, whatever the occupancy.  Group g waits for group g-1's last sweep
-// through a progress counter.  Band data crosses
-// workgroups (and XCDs, whose L2 caches are not coherent with each other), so
-// every band access is a relaxed device-scope atomic (coherent at device
-// level), and progress is published only after the step's stores completed.
+// Kernels: b = 16 runs k_chase_flow (lag-2 schedule, LDS window, loader and
+// storer waves, no per-step barrier); b = 32 runs the windowed k_chase_win
+// (lag 3, one barrier per step); larger b the direct k_chase.  In all of them a
+// persistent grid takes groups of W consecutive sweeps in increasing order from
+// a ticket counter, so the predecessor of every group being worked on is held by
+// a workgroup that is already running: no schedule can wait on a workgroup that
+// was never made resident, whatever the occupancy.  Group g waits for group
+// g-1's last sweep through a progress counter.  Band data crosses workgroups
+// (and XCDs, whose L2 caches are not coherent with each other) only as
+// device-scope accesses (coherent at device level), and progress is published
+// only after the stores it covers have completed.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -301,7 +302,7 @@ __global__ void k_chase(ChaseArgs L) {
 }
 
 // ---------------------------------------------------------------------------
-// Windowed chase (b = 16 or 32): the rows a group is working on live in LDS.
+// Windowed chase (b = 32): the rows a group is working on live in LDS.
 // ---------------------------------------------------------------------------
 //
 // The group's rows form a sliding window kept in an LDS ring buffer (row r in
@@ -589,243 +590,574 @@ __global__ void __launch_bounds__(512) k_chase_win(ChaseArgs L) {
 }
 
 // ---------------------------------------------------------------------------
-// Windowed chase with mover waves (b = 16): the window of k_chase_win, with all
-// global-memory traffic taken off the tasks' path.
+// Pipelined chase (b = 16): lag-2 schedule, reflectors formed by every lane
+// from a broadcast copy of the vector, row movers that keep global-memory
+// latency off the tasks' path, and no workgroup barrier per step.
 // ---------------------------------------------------------------------------
 //
-// Waves 0..W-1 only compute (wave i runs task t-3i of sweep s0+i at step t);
-// the kSpecMovers = 2 waves after them move rows, during the tasks of the same
-// step, side by side.  At step t the storer wave
-//   1. waits for its own stores of step t-1,
-//   2. (one lane) publishes the progress whose rows were stored at step t-2,
-//   3. stores the rows no sweep of the group touches after step t-1;
-// and the loader wave
-//   1. waits for its own loads of step t-1 and writes those rows (needed at
-//      step t+1) into the window,
-//   2. waits until the predecessor group finished the tasks step t+2 depends
-//      on, and requests the rows of step t+2.
-// One workgroup barrier ends a step.  Rows written in (3) are beyond every row
-// the tasks of step t touch, and rows stored in (4) are below them, so the
-// movers never race the tasks.  The hand-off between consecutive groups costs
-// about four steps.
+// Lag 2.  Task j of sweep s+1 and task j+2 of sweep s share exactly one band
+// element, (p, c) of the latter: its right reflector reads it as alpha and
+// overwrites it with beta at the very start, and the former's left update
+// (whose last row is p and last column c) reads and rewrites it near its end.
+// Every other element of the two tasks is disjoint, and tasks further apart
+// are disjoint, so the two may run in the same step if the left update of
+// sweep s+1 waits for the beta of sweep s: wave i publishes the step number
+// in an LDS flag right after writing its beta, and wave i+1 waits for it
+// before loading its left-update operands.  Wave i runs task t - 2i of sweep
+// s0 + i at step t, so a sweep costs two steps instead of three.
+//
+// Task arithmetic.  With x the vector to annihilate (x_0 = alpha, tail x_1..),
+// beta = -sgn(alpha) ||x||, v = (1, x_1 / (alpha - beta), ...) and
+// tau = (beta - alpha) / beta (LAPACK's dlarfg convention), the update of a
+// vector y is y - tau (v^T y) v with v^T y = y_0 + D / (alpha - beta) and
+// D = sum_{l >= 1} x_l y_l.  Every lane reads the whole of x (broadcast LDS
+// reads), so D starts as soon as the operands arrive, beside the norm, and no
+// lane exchange is needed for the norm or the coefficients; every lane forms
+// them with the same instructions, hence bitwise the same values.
+//
+// Movers and the schedule without a per-step barrier: see k_chase_flow.
 
-constexpr int kSpecMovers = 2;
-constexpr int kSpecMaxW = 6;
+__device__ __forceinline__ int uni_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Global-memory pointer types: accesses through them are global (not flat)
+// instructions, counted by vmcnt only, so in-flight loads never hold up a wait
+// on LDS operations.
+typedef __attribute__((address_space(1))) double glb_f64;
+typedef __attribute__((address_space(1))) f64x2 glb_f64x2;
+typedef __attribute__((address_space(1))) int glb_i32;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+constexpr int kDevScope = 16;  // buffer-access cache policy: sc1 (device scope)
+__device__ __forceinline__ int64_t uni_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
-__host__ __device__ inline int spec_rows(int b, int W) { return (3 * W + 6) * b; }
+// Ring slot (r - base) mod R by a multiply-high with m = floor(2^32 / R): the
+// quotient estimate is at most one below the true one for r - base < 2^24 (rows
+// are below 2^20), so one correction gives the remainder.
+__host__ __device__ inline uint32_t ring_magic(int R) { return (uint32_t)(0xffffffffu / (uint32_t)R); }
+__device__ __forceinline__ int ring_slot_m(int64_t r, int64_t base, int R, uint32_t m) {
+  const uint32_t d = (uint32_t)(r - base);
+  const uint32_t q = __umulhi(d, m);
+  uint32_t s = d - q * (uint32_t)R;
+  s = s >= (uint32_t)R ? s - (uint32_t)R : s;
+  return (int)s;
+}
 
-size_t chase_spec_lds_bytes(int b, int W) {
-  return ((size_t)(spec_rows(b, W) + 1) * (3 * b + 2) + (size_t)16 * b) * sizeof(double);  // ring + zero slot + reflector slots
+struct PipeRefl {
+  double beta, scal, tau;
+};
+
+// The task arithmetic below is written out operation by operation (explicit
+// fma where one is meant, no contraction of the rest), so that every copy of it
+// -- the two left-update paths of a task -- rounds identically and the chase is
+// bitwise the same for every schedule.
+
+// Sum over l = 1 .. B-1 of a_l * b_l in four interleaved partial sums, added
+// pairwise: the same order wherever it is used.
+template <int B>
+__device__ __forceinline__ double pipe_dot1(const double (&a)[B], const double (&b)[B]) {
+#pragma clang fp contract(off)
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+#pragma unroll
+  for (int l = 1; l < B; ++l) {
+    if ((l & 3) == 0) q0 = fma(a[l], b[l], q0);
+    if ((l & 3) == 1) q1 = fma(a[l], b[l], q1);
+    if ((l & 3) == 2) q2 = fma(a[l], b[l], q2);
+    if ((l & 3) == 3) q3 = fma(a[l], b[l], q3);
+  }
+  return (q0 + q1) + (q2 + q3);
 }
 
 template <int B>
-__global__ void __launch_bounds__(64 * (kSpecMaxW + kSpecMovers)) k_chase_spec(ChaseArgs L) {
+__device__ __forceinline__ PipeRefl pipe_refl(const double (&x)[B]) {
+#pragma clang fp contract(off)
+  const double ss = pipe_dot1<B>(x, x);
+  const double alpha = x[0];
+  PipeRefl r;
+  r.beta = alpha;
+  r.scal = 0.0;
+  r.tau = 0.0;
+  if (ss > 0.0) {
+    const double nrm = sqrt(fma(alpha, alpha, ss));
+    r.beta = alpha >= 0.0 ? -nrm : nrm;
+    r.scal = nr_div(1.0, alpha - r.beta);  // |alpha - beta| >= sqrt(ss): normal whenever ss > 0
+    r.tau = nr_div(r.beta - alpha, r.beta);
+  }
+  return r;
+}
+
+// y <- (I - tau v v^T) y, with D = sum_{l >= 1} x_l y_l (tau = 0 leaves y bitwise unchanged)
+template <int B>
+__device__ __forceinline__ void pipe_apply(const PipeRefl& r, const double (&x)[B], double (&y)[B], double D) {
+#pragma clang fp contract(off)
+  const double w = r.tau * fma(r.scal, D, y[0]);
+  const double ws = w * r.scal;
+  y[0] -= w;
+#pragma unroll
+  for (int l = 1; l < B; ++l) y[l] = fma(-ws, x[l], y[l]);
+}
+
+// Task (p, c) on the window, one wave.  `mine`: this wave's beta flag (set to t
+// after the right reflector's beta is written), `prev`: the flag of the wave of
+// the previous sweep when that sweep has a task at this step (else null).
+// Lanes past the last row (right update) or column (left update) read the first
+// one again and store nothing, so the loads need no branch.  Returns false if
+// the wait for `prev` gave up (*fail set elsewhere, or a 1 s bound).
+template <int B>
+__device__ __forceinline__ bool pipe_task(lds_f64* win, int R, uint32_t rmagic, int64_t s0, int64_t n, int64_t p,
+                                          int64_t c, int* mine, const int* prev, int t, const int* fail) {
+  constexpr int RS = 3 * B + 2, LO = B - 1;
+  const int lane = threadIdx.x & 63;
+  const int L = uni_i32((int)((n - c) < B ? (n - c) : B));
+  const int nr = uni_i32((int)(c + L - p - 1));                                  // rows p+1 .. c+L-1
+  const int nq = uni_i32((int)(((c + L + B) < n ? (c + L + B) : n) - c - 1));   // columns c+1 .. c+nq
+  const int dc = uni_i32((int)(c - p));
+  const int sp = uni_i32(ring_slot_m(p, s0, R, rmagic));
+  const int sc = uni_i32(ring_slot_m(c, s0, R, rmagic));
+
+  // ---------------- right reflector: row p, columns c .. c+B-1 ----------------
+  lds_f64* rowp = win + sp * RS + (dc + LO);
+  double x[B], y[B];
+#pragma unroll
+  for (int l = 0; l < B; ++l) x[l] = rowp[l];  // one address for every lane: broadcast
+  const int lr = lane < nr ? lane : 0;
+  int sr = sp + 1 + lr;
+  sr = sr >= R ? sr - R : sr;
+  lds_f64* row = win + sr * RS + (dc - 1 - lr + LO);  // element (p+1+lr, c+l) at row[l]
+#pragma unroll
+  for (int l = 0; l < B; ++l) y[l] = row[l];
+  double D = pipe_dot1<B>(x, y);
+  PipeRefl r = pipe_refl<B>(x);
+  if (lane < B) rowp[lane] = lane == 0 ? r.beta : 0.0;
+  if (lane == 0) __hip_atomic_store(mine, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  pipe_apply<B>(r, x, y, D);
+  if (lane < nr) {
+#pragma unroll
+    for (int l = 0; l < B; ++l) row[l] = y[l];
+  }
+
+  // ---------------- left reflector: column c, rows c .. c+B-1 ----------------
+  bool ok = true;
+  if (prev != nullptr && __hip_atomic_load(prev, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < t) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__hip_atomic_load(prev, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= t) break;
+      if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
+          __builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {  // 1 s at 100 MHz
+        ok = false;
+        break;
+      }
+    }
+  }
+  const int lq = lane < nq ? lane : 0;  // column c+1+lq
+  if (sc + B <= R && L == B) {
+    // rows c .. c+B-1 in consecutive slots: element (c+m, c) at colx[m (RS-1)],
+    // element (c+m, c+1+lq) at coly[m (RS-1)]
+    const lds_f64* colx = win + sc * RS + LO;
+    lds_f64* coly = win + sc * RS + (1 + lq + LO);
+#pragma unroll
+    for (int m = 0; m < B; ++m) x[m] = colx[m * (RS - 1)];
+#pragma unroll
+    for (int m = 0; m < B; ++m) y[m] = coly[m * (RS - 1)];
+    D = pipe_dot1<B>(x, y);
+    r = pipe_refl<B>(x);
+    if (lane < B) win[(sc + lane) * RS + LO - lane] = lane == 0 ? r.beta : 0.0;
+    pipe_apply<B>(r, x, y, D);
+    if (lane < nq) {
+#pragma unroll
+      for (int m = 0; m < B; ++m) coly[m * (RS - 1)] = y[m];
+    }
+  } else {
+    // wrapping window or rows past n - 1 (read from the zero slot R, never written)
+    int so[B];
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+      int sm = sc + m;
+      sm = sm >= R ? sm - R : sm;
+      so[m] = m < L ? sm : R;
+    }
+#pragma unroll
+    for (int m = 0; m < B; ++m) x[m] = win[so[m] * RS + LO - m];
+#pragma unroll
+    for (int m = 0; m < B; ++m) y[m] = win[so[m] * RS + 1 + lq - m + LO];
+    D = pipe_dot1<B>(x, y);
+    r = pipe_refl<B>(x);
+    if (lane < L) {
+      int sm = sc + lane;
+      sm = sm >= R ? sm - R : sm;
+      win[sm * RS + LO - lane] = lane == 0 ? r.beta : 0.0;
+    }
+    pipe_apply<B>(r, x, y, D);
+    if (lane < nq) {
+#pragma unroll
+      for (int m = 0; m < B; ++m)
+        if (m < L) win[so[m] * RS + 1 + lq - m + LO] = y[m];
+    }
+  }
+  return ok;
+}
+
+// Barrier-free schedule.  The waves of a workgroup synchronise through
+// counters in LDS instead of a workgroup barrier per step:
+//   s_done[i]  last step compute wave i has finished; wave i starts step t once
+//              wave i-1 finished step t-1 (and wave 0 once the rows of step t
+//              are in the window).  Every wave passes every step;
+//   s_filled   last step whose rows are in the window;
+//   s_stored   last duty whose rows have been read out of the window for storing
+//              (their slots may be refilled K duties later);
+//   s_conf     last duty whose stores are known to be complete in memory.
+// A wave that runs ahead of its successor is always safe (the later sweep only
+// falls further behind); one that would fall behind waits.  Two kinds of mover
+// waves take duties in turn.  Loader k (of ML) at duty t = k, k + ML, ... fills
+// the rows of step t + 1 (loaded at its previous duty) and loads those of step
+// t + ML + 1; it runs ahead of the compute waves.  Storer k (of MS) at duty
+// t = k, k + MS, ... reads out the rows no task touches after step t - 1 once
+// every compute wave has finished that step, stores them, waits for the stores
+// to complete and publishes the progress they allow; it trails the compute
+// waves.  Neither is on the compute waves' path, which carries only task
+// latency and counter hand-offs.
+//
+// Hand-off between groups.  Band rows cross workgroups (and XCDs, whose L2
+// caches are not coherent with each other) only as relaxed device-scope atomic
+// loads and stores, which go to the device's coherence point.  A group publishes
+// a progress value only after the stores it covers have completed there (the
+// mover's own wait on its memory counter, confirmed in duty order), and a group
+// issues the loads of rows only after it has read a progress value that covers
+// them; a compiler-only fence keeps the compiler from moving memory operations
+// across either point.  Agent-scope release/acquire fences would add a
+// write-back or an invalidation of the whole L2 cache per hand-off; measured in
+// this kernel they lengthen every mover duty by microseconds, so the ordering
+// rests on completion of device-scope accesses instead.
+
+constexpr int kFlowLoaders = 2;  // ML
+constexpr int kFlowStorers = 2;  // MS
+constexpr int kFlowSlack = 2;  // K: extra ring rows (in units of b) between storing and refilling a slot
+constexpr int kFlowMaxW = 8;
+constexpr int kFlowNarrowW = 4;  // widths up to this run an instantiation with 256 VGPRs per lane
+
+__host__ __device__ inline int flow_rows(int b, int W) { return (2 * W + 3 + kFlowSlack) * b; }
+
+size_t chase_flow_lds_bytes(int b, int W) {
+  return (size_t)(flow_rows(b, W) + 1) * (3 * b + 2) * sizeof(double);  // ring + zero slot
+}
+
+// Wait until the LDS counter reaches v (acquire).  Gives up (false) when *fail
+// is set or after 10 s.
+__device__ __forceinline__ bool lds_wait_ge(const int* ctr, int v, const int* fail) {
+  if (uni_i32(__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) >= v) return true;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (uni_i32(__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) >= v) return true;
+    if (uni_i32(__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0 ||
+        __builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull)
+      return false;
+  }
+}
+__device__ __forceinline__ void lds_set(int* ctr, int v) {
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(ctr, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int B, int ML, int MS, int K, int WMAX>
+__global__ void __launch_bounds__(64 * (WMAX + ML + MS)) k_chase_flow(ChaseArgs Lg) {
   constexpr int RW = 3 * B, RS = RW + 2, MT = 64;
   constexpr int KP = (B * RW / 2 + MT - 1) / MT;  // pairs of doubles per mover lane for B rows
   extern __shared__ __align__(16) double lds[];
-  __shared__ int s_flag;
-  const int W = L.W;
-  const int R = spec_rows(B, W);
+  __shared__ int s_done[WMAX], s_beta[WMAX];
+  __shared__ int s_filled, s_stored, s_conf, s_fail;
+  const int W = uni_i32(Lg.W);
+  const int R = (2 * W + 3 + K) * B;
+  const uint32_t rmagic = ring_magic(R);
   lds_f64* win = (lds_f64*)lds;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), tid = threadIdx.x;  // wv: wave-uniform
+  const int wv = uni_i32(threadIdx.x >> 6);
+  const int tid = threadIdx.x;
+  const int mt = tid & 63;
   const bool mover = wv >= W;
-  const bool storer = wv == W;  // the first mover wave stores and publishes, the second loads
-  const int mt = tid & 63;      // lane within the mover wave
+  const int mk = wv - W;  // mover index (mover waves only)
   for (int e = tid; e < RS; e += blockDim.x) win[R * RS + e] = 0.0;  // zero slot
+
+  // pair k of a mover lane within a block of rows: row prow[k], columns pcol[k], pcol[k] + 1
+  int prow[KP], pcol[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int q = mt + k * MT;
+    prow[k] = q / (RW / 2);
+    pcol[k] = 2 * (q % (RW / 2));
+  }
 
   for (;;) {
     int gi;
-    const ChaseArgs a = take_group(L, gi);
+    const ChaseArgs a = take_group(Lg, gi);
     if (gi < 0) break;
-    const int64_t n = a.n;
+    gi = uni_i32(gi);
+    const int64_t n = uni_i64(a.n);
+    double* Bs = a.Bs;
+    glb_i32* progress = (glb_i32*)a.progress;
+    glb_i32* err = (glb_i32*)a.err;
     const int64_t s0 = (int64_t)gi * W;
-    const int nsw = (int)((n - 1 - s0) < W ? (n - 1 - s0) : W);
+    const int sbase = (int)(s0 * RW * (int64_t)sizeof(double));  // byte offset of row s0 (rows below 2^20)
+    const int nsw = uni_i32((int)((n - 1 - s0) < W ? (n - 1 - s0) : W));
     const int64_t sl = s0 + nsw - 1;
+    const int first_total = ntasks_b<B>(s0, n);
+    const int last_total = ntasks_b<B>(sl, n);
+    const int prev_total = gi > 0 ? ntasks_b<B>(s0 - 1, n) : 0;
     int tend = 0;
     for (int i = 0; i < nsw; ++i) {
-      const int te = 3 * i + ntasks_b<B>(s0 + i, n);
+      const int te = 2 * i + ntasks_b<B>(s0 + i, n);
       tend = te > tend ? te : tend;
     }
-    const int prev_total = gi > 0 ? ntasks_b<B>(s0 - 1, n) : 0;
-    const int last_total = ntasks_b<B>(sl, n);
-    const int first_total = ntasks_b<B>(s0, n);
-    auto slot = [&](int64_t r) -> int { return ring_slot(r, s0, R); };
-    // rows the group's first sweep needs up to (and including) step t: [s0, front_end(t))
-    auto front_end = [&](int t) -> int64_t {
-      const int tt = t < first_total - 1 ? t : first_total - 1;
-      const int64_t e = s0 + 1 + (int64_t)(tt + 1) * B;
+    // rows the group's first sweep needs up to (and including) step u: [s0, fe(u))
+    auto fe = [&](int u) -> int64_t {
+      if (u < 0) return s0;
+      const int uu = u < first_total - 1 ? u : first_total - 1;
+      const int64_t e = s0 + 1 + (int64_t)(uu + 1) * B;
       return e < n ? e : n;
     };
-    // rows no sweep of the group touches after step t
+    // rows no sweep of the group touches after step t (rows below fe(t) only): the
+    // lowest front of the unfinished sweeps.  The last sweep finishes last (sweeps
+    // of one group differ by at most one task, and it starts 2 steps after its
+    // predecessor); once started its front is the lowest, and before that the
+    // first sweep not yet started (front = its first row) is.
     auto final_after = [&](int t) -> int64_t {
-      int64_t lo = n;
-      for (int i = 0; i < nsw; ++i) {
-        const int jn = t + 1 - 3 * i;
-        if (jn < ntasks_b<B>(s0 + i, n)) {
-          const int64_t f = sweep_front(s0 + i, jn, B);
-          lo = f < lo ? f : lo;
-        }
+      const int64_t f_e = fe(t);
+      const int jn = t + 1 - 2 * (nsw - 1);
+      if (jn >= last_total) return f_e;
+      int64_t f;
+      if (jn <= 0) {
+        const int i0 = (t + 2) / 2 > 0 ? (t + 2) / 2 : 0;  // first sweep whose task t+1-2i is not positive
+        f = s0 + i0;
+      } else {
+        f = sweep_front(sl, jn, B);
       }
-      const int64_t cap = front_end(t);
-      return lo < cap ? lo : cap;
+      return f < f_e ? f : f_e;
     };
-    // tasks of the last sweep completed after step t
-    auto done_after = [&](int t) -> int {
-      int d = t - 3 * (nsw - 1) + 1;
-      return d < 0 ? 0 : (d > last_total ? last_total : d);
+    // progress the successor may rely on once every step up to t is finished and
+    // the rows below Lr are stored: tasks of the last sweep done, capped by the
+    // rows the successor's step P-3 needs (below sl + 2 + (P-2) B)
+    auto allowed = [&](int t, int64_t Lr) -> int {
+      int d = t - 2 * (nsw - 1) + 1;
+      d = d < 0 ? 0 : (d > last_total ? last_total : d);
+      if (Lr < n) {
+        const int64_t q = Lr - sl - 2;
+        const int br = q >= 0 ? (int)(q / B) + 2 : 0;
+        d = br < d ? br : d;
+      }
+      return d;
     };
-    // progress that rows [.., L) written back allow (the next group's step j
-    // needs rows below sl + 2 + (j+1) b and progress j + 3)
-    auto by_rows = [&](int64_t L) -> int { return L - sl - 1 >= 0 ? (int)((L - sl - 1) / B) + 1 : 0; };
-    // each mover wave waits until the previous group's last sweep completed `need` tasks (bounded)
-    auto wait_prev = [&](int need) {
-      if (gi == 0) return;
+    auto giveup = [&]() {
+      if (mt == 0) {
+        __hip_atomic_fetch_add(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&s_fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    };
+    // bounded wait (one mover wave) until the predecessor's progress reaches `need`
+    auto wait_prev = [&](int need, int& known) -> bool {
       need = need < prev_total ? need : prev_total;
+      if (gi == 0 || known >= need) return true;
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      while (__hip_atomic_load(&a.progress[gi - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      for (;;) {
+        known = uni_i32(__hip_atomic_load(&progress[gi - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (known >= need) return true;
         if (__builtin_amdgcn_s_memrealtime() - t0 > 1000000000ull ||  // 10 s at 100 MHz
-            __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          if ((tid & 63) == 0) atomicAdd(a.err, 1);
-          s_flag = 1;
-          return;
-        }
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            __hip_atomic_load(&s_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+          return false;
         __builtin_amdgcn_s_sleep(1);
       }
     };
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-    // row movers: a block of rows [r0, r1) is contiguous in the chase storage (row
-    // stride RW = 3B); it is moved as pairs of doubles, pair q = (row r0 + q / (RW/2),
-    // columns 2 (q % (RW/2)) and the next), thread mt taking pairs mt + k MT.  On the
-    // LDS side a pair is one 16-byte access (slot stride and RW are even).
-    auto mv_load = [&](int64_t r0, int64_t r1, f64x2 (&buf)[KP]) {
-      const int np = (int)(r1 - r0) * (RW / 2);
-      const double* src = a.Bs + r0 * RW + 2 * mt;
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        const bool ok = mt + k * MT < np;
-        buf[k].x = ok ? bld(src + 2 * k * MT) : 0.0;
-        buf[k].y = ok ? bld(src + 2 * k * MT + 1) : 0.0;
-      }
-    };
-    // pair k of this thread: row prow[k] of the block, columns pcol[k], pcol[k] + 1
-    // (the same for every block, so computed once)
-    int prow[KP], pcol[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int q = mt + k * MT;
-      prow[k] = q / (RW / 2);
-      pcol[k] = 2 * (q % (RW / 2));
-    }
+    auto slot = [&](int64_t r) -> int { return ring_slot_m(r, s0, R, rmagic); };
     auto pair_lds = [&](int s_r0, int k) -> lds_f64x2* {
-      int sl = s_r0 + prow[k];
-      sl = sl >= R ? sl - R : sl;
-      return (lds_f64x2*)(win + sl * RS + pcol[k]);
+      int sq = s_r0 + prow[k];
+      sq = sq >= R ? sq - R : sq;
+      return (lds_f64x2*)(win + sq * RS + pcol[k]);
     };
-    auto mv_fill = [&](int64_t r0, int64_t r1, const f64x2 (&buf)[KP]) {
+    // Band rows move as 16-byte buffer accesses at device scope (sc1: coherent at
+    // the device level, like the relaxed device-scope atomics they stand for);
+    // the resource covers the matrix's n rows, so nothing outside them is touched.
+    const __amdgpu_buffer_rsrc_t brs =
+        __builtin_amdgcn_make_buffer_rsrc(Bs, (short)0, (int)(n * RW * (int64_t)sizeof(double)), 0x00020000);
+    // global <-> registers <-> window for a block of at most B rows [r0, r1)
+    auto blk_load = [&](int64_t r0, int64_t r1, f64x2 (&buf)[KP]) {
+      const int np = (int)(r1 - r0) * (RW / 2);
+      const int base = (int)((r0 - s0) * RW * (int64_t)sizeof(double));
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+        if (mt + k * MT < np)
+          buf[k] = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(brs, (mt + k * MT) * 16, base + sbase,
+                                                                                    kDevScope));
+    };
+    auto blk_fill = [&](int64_t r0, int64_t r1, const f64x2 (&buf)[KP]) {
       const int rows = (int)(r1 - r0);
       const int s_r0 = slot(r0);
 #pragma unroll
       for (int k = 0; k < KP; ++k)
         if (prow[k] < rows) *pair_lds(s_r0, k) = buf[k];
     };
-    auto mv_store = [&](int64_t r0, int64_t r1) {
-      // up to B rows per batch (more only when the last sweep starts): LDS reads, then stores
+    // rows [r0, r1) read out of the window and stored at device scope; `read_out`
+    // is called once every row has left the window (before the last stores issue)
+    auto store_rows = [&](int64_t r0, int64_t r1, auto read_out) {
       for (int64_t rb = r0; rb < r1; rb += B) {
         const int64_t re = r1 - rb < B ? r1 : rb + B;
-        const int np = (int)(re - rb) * (RW / 2);
         const int rows = (int)(re - rb);
+        const int np = rows * (RW / 2);
         const int s_r0 = slot(rb);
         f64x2 vals[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) vals[k] = prow[k] < rows ? *pair_lds(s_r0, k) : f64x2{0.0, 0.0};
-        double* dst = a.Bs + rb * RW + 2 * mt;
+        if (re == r1) read_out();
+        const int base = (int)((rb - s0) * RW * (int64_t)sizeof(double));
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-          if (mt + k * MT < np) {
-            bst(dst + 2 * k * MT, vals[k].x);
-            bst(dst + 2 * k * MT + 1, vals[k].y);
-          }
+          if (mt + k * MT < np)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, vals[k]), brs, (mt + k * MT) * 16,
+                                                   base + sbase, kDevScope);
       }
+      if (r0 >= r1) read_out();
     };
-    // prologue: rows of steps 0 and 1, loaded directly
-    if (mover && !storer) {
-      wait_prev(4);
-      if (!s_flag) {
-        const int64_t hi1 = front_end(1);
-        for (int64_t rb = s0; rb < hi1; rb += B) {
+
+    if (tid == 0) {
+      s_filled = -1;
+      s_stored = -1;
+      s_conf = -1;
+      s_fail = 0;
+    }
+    if (tid < WMAX) {
+      s_done[tid] = -1;
+      s_beta[tid] = -1;
+    }
+    __syncthreads();
+    // prologue: rows of steps 0 .. ML, loaded by the loaders together (after the
+    // predecessor's progress allows step ML)
+    int known = 0;
+    if (mover && mk < ML) {
+      if (wait_prev(ML + 3, known)) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int64_t hi = fe(ML);
+        for (int64_t rb = s0 + (int64_t)mk * B; rb < hi; rb += (int64_t)ML * B) {
           f64x2 buf[KP];
-          const int64_t re = hi1 - rb < B ? hi1 : rb + B;
-          mv_load(rb, re, buf);
-          mv_fill(rb, re, buf);
+          const int64_t re = hi - rb < B ? hi : rb + B;
+          blk_load(rb, re, buf);
+          blk_fill(rb, re, buf);
         }
+      } else {
+        giveup();
       }
     }
     __syncthreads();
-    int64_t lo = s0;         // rows below lo have been stored
-    int64_t lo_hist[3] = {s0, s0, s0};  // lo after the stores of steps t-1, t-2, t-3
-    int published = 0;
-    f64x2 regs[KP];
-    for (int t = 0; t < tend && !s_flag; ++t) {
-      CHASE_MARK(gi, t, 0);
-      if (!mover) {
-        if (wv < nsw) {
-          const int64_t s = s0 + wv;
-          const int jt = t - 3 * wv;
-          if (jt >= 0 && jt < ntasks_b<B>(s, n)) {
+    if (tid == 0) s_filled = ML;
+    __syncthreads();
+
+    if (!mover) {
+      if (wv < nsw) {
+        const int64_t s = s0 + wv;
+        const int nt = ntasks_b<B>(s, n);
+        const int ntp = wv > 0 ? ntasks_b<B>(s - 1, n) : 0;
+        for (int t = 0; t < tend; ++t) {
+          const bool ok = wv == 0 ? lds_wait_ge(&s_filled, t, &s_fail) : lds_wait_ge(&s_done[wv - 1], t - 1, &s_fail);
+          if (!ok) {
+            giveup();
+            break;
+          }
+          CHASE_MARK_IF(mt == 0 && wv == 0, gi, t, 0);
+          const int jt = t - 2 * wv;
+          if (jt >= 0 && jt < nt) {
             const int64_t c = s + 1 + (int64_t)jt * B;
             const int64_t p = jt == 0 ? s : c - B;
-            win_task<B>(win, win + (R + 1) * RS + wv * B, R, R, s0, n, p, c);
+            // the previous sweep's task jt+2 runs at the same step: wait for its beta
+            const int* prevf = (wv > 0 && jt + 2 < ntp) ? &s_beta[wv - 1] : nullptr;
+            if (!pipe_task<B>(win, R, rmagic, s0, n, p, c, &s_beta[wv], prevf, t, &s_fail)) {
+              giveup();
+              break;
+            }
           }
+          lds_set(&s_done[wv], t);
+          CHASE_MARK_IF(mt == 0 && wv == 0, gi, t, 1);
+          CHASE_MARK_IF(mt == 0 && wv == nsw - 1, gi, t, 2);
         }
-        CHASE_MARK(gi, t, 1);
-      } else if (storer) {
-        // 1. own stores of step t-1 complete
-        __builtin_amdgcn_s_waitcnt(0);
-        CHASE_MARK_IF(mt == 0, gi, t, 3);
-        // 2. publish: the rows stored at step t-2 are long complete
-        if (mt == 0 && t >= 2) {
-          int P = done_after(t - 3 >= 0 ? t - 3 : -1);
-          const int br = by_rows(lo_hist[1]);
-          P = br < P ? br : P;
-          P = P < last_total - 1 ? P : last_total - 1;
-          if (P > published) {
-            published = P;
-            __hip_atomic_store(&a.progress[gi], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
-        // 3. store the rows final after step t-1
-        if (t >= 1) {
-          const int64_t nlo = final_after(t - 1);
-          mv_store(lo, nlo);
-          lo = nlo > lo ? nlo : lo;
-        }
-        lo_hist[2] = lo_hist[1];
-        lo_hist[1] = lo_hist[0];
-        lo_hist[0] = lo;
-        CHASE_MARK_IF(mt == 0, gi, t, 4);
-      } else {
-        // 1. own loads of step t-1 complete; their rows (needed at step t+1) into the window
-        __builtin_amdgcn_s_waitcnt(0);
-        if (t >= 1) mv_fill(front_end(t), front_end(t + 1), regs);
-        // 2. rows of step t+2
-        wait_prev(t + 5);
-        CHASE_MARK_IF(mt == 0, gi, t, 5);
-        if (!s_flag) mv_load(front_end(t + 1), front_end(t + 2), regs);
-        CHASE_MARK_IF(mt == 0, gi, t, 6);
       }
-      __syncthreads();
-      CHASE_MARK(gi, t, 2);
-    }
-    // epilogue: store the rest of the window, then mark the group complete
-    if (storer) {
+    } else if (mk < ML) {
+      // loader mk: duties t = mk, mk + ML, ...
+      f64x2 regs[KP];
+      int pend = 0;
+      bool have_pend = false;
+      for (int t = mk; t < tend; t += ML) {
+        CHASE_MARK_IF(mt == 0, gi, t, 3);
+        // rows of step t + 1 (loaded at duty t - ML) into the window, in step order,
+        // into slots whose rows were read out at least K duties ago
+        if (t >= ML) {
+          __builtin_amdgcn_s_waitcnt(0);
+          if (!lds_wait_ge(&s_stored, t - 1 - K, &s_fail) || !lds_wait_ge(&s_filled, t, &s_fail)) {
+            giveup();
+            break;
+          }
+          blk_fill(fe(t), fe(t + 1), regs);
+          lds_set(&s_filled, t + 1);
+        }
+        CHASE_MARK_IF(mt == 0, gi, t, 4);
+        // rows of step t + ML + 1, once the predecessor's progress allows them
+        if (have_pend) known = pend > known ? pend : known;
+        const int64_t r0 = fe(t + ML), r1 = fe(t + ML + 1);
+        if (r1 > r0) {
+          if (!wait_prev(t + ML + 4, known)) {
+            giveup();
+            break;
+          }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          blk_load(r0, r1, regs);
+        }
+        CHASE_MARK_IF(mt == 0, gi, t, 5);
+        if (gi > 0) {
+          pend = __hip_atomic_load(&progress[gi - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          have_pend = true;
+        }
+      }
       __builtin_amdgcn_s_waitcnt(0);
-      mv_store(lo, front_end(tend));
+    } else {
+      // storer mk - ML: duties t = mk - ML, mk - ML + MS, ...
+      for (int t = mk - ML; t < tend; t += MS) {
+        // rows final after step t - 1, read out in duty order once every wave has
+        // finished that step (a wave may finish a step before its predecessor
+        // does: the order only binds starts), then stored
+        bool ready = lds_wait_ge(&s_stored, t - 1, &s_fail);
+        for (int i = nsw - 1; i >= 0 && ready; --i) ready = lds_wait_ge(&s_done[i], t - 1, &s_fail);
+        if (!ready) {
+          giveup();
+          break;
+        }
+        CHASE_MARK_IF(mt == 0, gi, t, 6);
+        const int64_t hi = final_after(t - 1);
+        store_rows(final_after(t - 2), hi, [&]() { lds_set(&s_stored, t); });
+        // stores complete: confirm in duty order and publish what they allow
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (!lds_wait_ge(&s_conf, t - 1, &s_fail)) {
+          giveup();
+          break;
+        }
+        if (mt == 0) {
+          const int P = allowed(t - 1, hi);
+          if (P > 0)
+            __hip_atomic_fetch_max(&progress[gi], P < last_total ? P : last_total - 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        lds_set(&s_conf, t);
+        CHASE_MARK_IF(mt == 0, gi, t, 7);
+      }
       __builtin_amdgcn_s_waitcnt(0);
     }
+    // epilogue: every wave is through its steps; store the rest of the window, then
+    // mark the group complete
     __syncthreads();
-    if (storer && mt == 0 && !s_flag)
-      __hip_atomic_store(&a.progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool failed = __hip_atomic_load(&s_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+    if (mover && mk == ML && !failed) {
+      store_rows(final_after(tend - 2), fe(tend - 1), []() {});
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (mt == 0)
+        __hip_atomic_fetch_max(&progress[gi], last_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
   }
 }
@@ -846,24 +1178,24 @@ __global__ void k_chase_extract_b(const ChaseArgs* __restrict__ tab) {
   chase_extract_body(a.Bs, a.ldb, a.n, a.b, a.d, a.e);
 }
 
-static bool use_spec(int b, int W) { return b == 16 && W <= kSpecMaxW && chase_spec_lds_bytes(b, W) <= 159 * 1024; }
-static bool use_window(int b, int W) {
-  return !use_spec(b, W) && (b == 16 || b == 32) && chase_win_lds_bytes(b, W) <= 159 * 1024;
-}
+static bool use_pipe(int b, int W) { return b == 16 && W <= kFlowMaxW && chase_flow_lds_bytes(b, W) <= 159 * 1024; }
+static bool use_window(int b, int W) { return b == 32 && chase_win_lds_bytes(b, W) <= 159 * 1024; }
 
 static const void* chase_fn(int b, int W) {
-  if (use_spec(b, W)) return (const void*)k_chase_spec<16>;
-  if (use_window(b, W)) return b == 16 ? (const void*)k_chase_win<16> : (const void*)k_chase_win<32>;
+  if (use_pipe(b, W))
+    return W <= kFlowNarrowW ? (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>
+                             : (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>;
+  if (use_window(b, W)) return (const void*)k_chase_win<32>;
   return (const void*)k_chase;
 }
 
 static int chase_threads(int b, int W) {
-  if (use_spec(b, W)) return 64 * (W + kSpecMovers);
-  return use_window(b, W) ? 64 * (W > WinGeom<16>::MIN_WAVES ? W : WinGeom<16>::MIN_WAVES) : 64 * W;
+  if (use_pipe(b, W)) return 64 * (W + kFlowLoaders + kFlowStorers);
+  return use_window(b, W) ? 64 * (W > WinGeom<32>::MIN_WAVES ? W : WinGeom<32>::MIN_WAVES) : 64 * W;
 }
 
 static size_t chase_launch_lds(int b, int W) {
-  if (use_spec(b, W)) return chase_spec_lds_bytes(b, W);
+  if (use_pipe(b, W)) return chase_flow_lds_bytes(b, W);
   return use_window(b, W) ? chase_win_lds_bytes(b, W) : chase_lds_bytes(b, W);
 }
 
@@ -890,8 +1222,12 @@ static hipError_t launch_chase_kernel(const ChaseArgs& a, int grid, hipStream_t 
   if (e != hipSuccess) return e;
   {
     const dim3 block(chase_threads(a.b, a.W));
-    if (fn == (const void*)k_chase_spec<16>) hipLaunchKernelGGL(k_chase_spec<16>, dim3(grid), block, lds, st, a);
-    else if (fn == (const void*)k_chase_win<16>) hipLaunchKernelGGL(k_chase_win<16>, dim3(grid), block, lds, st, a);
+    if (fn == (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>)
+      hipLaunchKernelGGL((k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>), dim3(grid), block,
+                         lds, st, a);
+    else if (fn == (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>)
+      hipLaunchKernelGGL((k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>), dim3(grid), block, lds,
+                         st, a);
     else if (fn == (const void*)k_chase_win<32>) hipLaunchKernelGGL(k_chase_win<32>, dim3(grid), block, lds, st, a);
     else hipLaunchKernelGGL(k_chase, dim3(grid), block, lds, st, a);
   }
