@@ -219,6 +219,30 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   }
 
   PANEL_MARK(slot, 1);
+  // Compact-WY factor T (upper triangular, LAPACK's forward columnwise form):
+  // T[j][j] = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] Y[0:j, j] with
+  // Y[k][j] = v_k^T v_j, which the column loop collects in Tl's strict upper
+  // part during iteration j.  For tiles up to 32 wave 0 forms column j-1 of T
+  // right after the barrier of iteration j (its own columns are finished by
+  // then, or nearly), lane i holding row i of T in registers, so T costs no
+  // time of its own; wider tiles build T after the loop by recursive doubling.
+  constexpr bool kTinLoop = TILE <= 32;
+  T trow[kTinLoop ? TILE : 1];
+#pragma unroll
+  for (int k = 0; k < (kTinLoop ? TILE : 1); ++k) trow[k] = T(0);
+  auto t_column = [&](int jj) {
+    if constexpr (kTinLoop) {
+      const T tj = taus[jj];
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < TILE; ++k)
+        if (k < jj && k >= l) acc += trow[k] * Tl[k * LDT + jj];
+      const T val = l < jj ? -tj * acc : (l == jj ? tj : T(0));
+#pragma unroll
+      for (int k = 0; k < TILE; ++k)
+        if (k == jj) trow[k] = val;
+    }
+  };
   // ---- Householder loop over the panel columns ----
   for (int j = 0; j < kr; ++j) {
     const int ow = j / CPT, oc = j % CPT;
@@ -262,6 +286,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
       if (l == 0) { taus[j] = (T)tau; Tl[j * LDT + j] = (T)tau; }
     }
     __syncthreads();
+    if (kTinLoop && w == 0 && j >= 1) t_column(j - 1);
     const T tau = taus[j];
     // v is kept in registers when the chunk leaves room for it, else re-read from LDS
     constexpr bool kCacheV = RPT * ((int)sizeof(T) / 4) * (CPT + 1) <= 96;
@@ -295,8 +320,20 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   __syncthreads();
 
   PANEL_MARK(slot, 2);
-  // ---- compact-WY factor: T = inverse of (diag(1/tau) + strict upper of V^T V), by doubling ----
-  for (int bs = 1; bs < kr; bs *= 2) {
+  if constexpr (kTinLoop) {
+    // last column of T, then the rows of T into Tl for the output stage
+    if (w == 0 && kr >= 1) {
+      t_column(kr - 1);
+      if (l < TILE) {
+#pragma unroll
+        for (int k = 0; k < TILE; ++k)
+          if (k >= l) Tl[l * LDT + k] = trow[k];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- (wider tiles) T = inverse of (diag(1/tau) + strict upper of V^T V), by doubling ----
+  for (int bs = 1; !kTinLoop && bs < kr; bs *= 2) {
     const int npair = (kr + 2 * bs - 1) / (2 * bs);
     // M = Y_AB * T_BB
     for (int t = threadIdx.x; t < npair * bs * bs; t += blockDim.x) {
