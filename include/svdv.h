@@ -81,7 +81,10 @@ typedef struct {
  * to S[0 .. min(m,n)-1] in A's dtype, descending and non-negative.
  * m == 0 or n == 0: returns SVDV_OK and writes nothing.
  * Non-finite input propagates NaN into S (no check on this path).
- * The tuned default configuration for (m, n, dtype) is used.
+ * The tuned default configuration for (m, n, dtype) is used: the auto-tuner's
+ * measured best (Eq. 1's argmin) of the cell of the same dtype nearest to
+ * min(m, n) on a log scale, compiled into the library from its tuned table
+ * (svdv_default_config returns it).
  */
 int svd_values(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, void* S, void* stream);
 

@@ -3,6 +3,7 @@
 // per-(device, stream) workspace cache and the dispatch to the HIP kernels.
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -130,19 +131,45 @@ int check_config_impl(int64_t m, int64_t n, int dtype, const svdv_config& c) {
   return SVDV_OK;
 }
 
+struct TunedCell {
+  int64_t n;
+  int32_t dtype, tile, threads, inner_block, sweep_width;
+};
+#include "tuned_table.inc"
+
+// The default configuration: the auto-tuner's measured best of the cell with
+// the same dtype whose size is nearest to min(m, n) on a log scale (ties go to
+// the larger cell), if the library accepts it for (m, n); otherwise tile 16 with
+// the widest trailing-update workgroup that fits its registers (1024 threads in
+// float32, 256 in float64), inner block 1 and sweep width 4.
 svdv_config default_config(int64_t m, int64_t n, int dtype) {
-  // The auto-tuner's best configuration for the dense n = 4096 float32 cell
-  // (tile 16, 1024 threads, inner block 1, sweep width 4); float64 keeps tile 16
-  // and the sweep width with 256 threads, the widest workgroup whose trailing
-  // update fits its registers in float64.
-  (void)m;
-  (void)n;
   svdv_config c;
   c.tile = 16;
   c.threads = dtype == SVDV_F32 ? 1024 : 256;
   c.inner_block = 1;
   c.sweep_width = 4;
   c.update_precision = 0;
+  const double k = (double)std::max<int64_t>(1, std::min(m, n));
+  const TunedCell* best = nullptr;
+  double bd = 0.0;
+  for (const TunedCell& t : kTunedCells) {
+    if (t.dtype != dtype || t.n <= 0) continue;
+    const double d = std::fabs(std::log2((double)t.n) - std::log2(k));
+    if (!best || d < bd - 1e-12 || (std::fabs(d - bd) <= 1e-12 && t.n > best->n)) {
+      best = &t;
+      bd = d;
+    }
+  }
+  if (best) {
+    svdv_config t = c;
+    t.tile = best->tile;
+    t.threads = best->threads;
+    t.inner_block = best->inner_block;
+    t.sweep_width = best->sweep_width;
+    const std::string saved = g_last_error;
+    if (check_config_impl(m, n, dtype, t) == SVDV_OK) c = t;
+    g_last_error = saved;
+  }
   return c;
 }
 

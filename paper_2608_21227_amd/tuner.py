@@ -62,8 +62,15 @@ def read_db(path: str) -> list[dict]:
 
 
 def append_db(path: str, rec: dict) -> None:
+    """Append one record; a torn last line (an interrupted write, no newline) is
+    closed first so the new record starts a line of its own."""
+    torn = False
+    if os.path.exists(path) and os.path.getsize(path) > 0:
+        with open(path, "rb") as f:
+            f.seek(-1, os.SEEK_END)
+            torn = f.read(1) != b"\n"
     with open(path, "a") as f:
-        f.write(json.dumps(rec) + "\n")
+        f.write(("\n" if torn else "") + json.dumps(rec) + "\n")
         f.flush()
         os.fsync(f.fileno())
 
