@@ -29,6 +29,7 @@ struct ChunkQRArgs {
   T* V;               // Householder vectors, chunk c at rows [c*chunk_rows, ...), leading dim ldv
   int64_t ldv;
   T* Tm;              // compact-WY factors, chunk c at Tm + c*TILE*TILE (TILE x TILE column-major)
+  int32_t hp;         // float32 storage factored in float64 arithmetic (BF16/FP16 trailing updates)
 };
 
 template <typename T>
@@ -127,7 +128,8 @@ hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int tr
 template <typename T> int chunk_qr_hmax(int tile);
 template <typename T> hipError_t launch_chunk_qr(int tile, const ChunkQRArgs<T>& a, hipStream_t st);
 // Batched forms (argument tables in device memory, one entry per matrix).
-template <typename T> hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, hipStream_t st);
+template <typename T> hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, int hp,
+                                                          hipStream_t st);
 template <typename T>
 hipError_t launch_stage_in_batched(const BatchMat<T>* tab, int count, unsigned long long* amax_all, int64_t max_elems,
                                    hipStream_t st);

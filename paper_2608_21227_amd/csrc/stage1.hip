@@ -17,6 +17,8 @@
 // chunk's rows twice (V^T C, then the rank-k update); nothing is shared between
 // waves, so no LDS and no barriers are needed.
 #include <algorithm>
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -131,19 +133,22 @@ __global__ void k_copy_scale(const T* __restrict__ A, int64_t m, int64_t n, int6
 // Thread layout: NW = 16 waves; wave w owns columns [w*CPT, (w+1)*CPT); lane l
 // owns rows q = i*64 + l, i < RPT.  Column sums are wave reductions.
 
-template <typename T, int TILE, int RPT>
+template <typename TC, int TILE, int RPT>
 struct ChunkQRCfg {
   static constexpr int NW = 16;
   static constexpr int CPT = TILE / NW;
   static constexpr int HMAX = 64 * RPT;
   // 64-row blocks transposed per barrier pair when loading (stage area <= 64 KiB)
-  static constexpr int CQB0 = (64 * 1024) / (64 * (TILE + 1) * (int)sizeof(T));
+  static constexpr int CQB0 = (64 * 1024) / (64 * (TILE + 1) * (int)sizeof(TC));
   static constexpr int CQB = CQB0 >= RPT ? RPT : (CQB0 >= 8 ? 8 : (CQB0 >= 4 ? 4 : (CQB0 >= 2 ? 2 : 1)));
 };
 
-template <typename T, int TILE, int RPT>
+// T: storage type of the matrix, V and T factors; TC: arithmetic type of the
+// factorisation (float64 for float32 storage when the trailing updates run in
+// BF16/FP16: the panel factorisation itself stays float64 there).
+template <typename T, int TILE, int RPT, typename TC = T>
 __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int c) {
-  typedef ChunkQRCfg<T, TILE, RPT> C;
+  typedef ChunkQRCfg<TC, TILE, RPT> C;
   constexpr int CPT = C::CPT;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t row0 = (int64_t)c * a.chunk_rows;
@@ -153,14 +158,14 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // LDS: stage [CQB*64][TILE+1] (also reused as Mtmp at the end) | vbuf[2][HMAX] | taus[TILE] | Tl[TILE][TILE+1]
-  T* stage = reinterpret_cast<T*>(smem_raw);
-  T* Mtmp = stage;
-  T* vbuf = stage + C::CQB * 64 * (TILE + 1);
-  T* taus = vbuf + 2 * C::HMAX;
-  T* Tl = taus + TILE;
+  TC* stage = reinterpret_cast<TC*>(smem_raw);
+  TC* Mtmp = stage;
+  TC* vbuf = stage + C::CQB * 64 * (TILE + 1);
+  TC* taus = vbuf + 2 * C::HMAX;
+  TC* Tl = taus + TILE;
   constexpr int LDT = TILE + 1;
 
-  T x[RPT][CPT];
+  TC x[RPT][CPT];
 
 #ifdef SVDV_PANEL_TRACE
   __shared__ int s_slot;
@@ -176,11 +181,11 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   // (coalesced along rows).  Otherwise (LQ sweep) threads read along the
   // memory-contiguous columns and the blocks are transposed through LDS, CQB
   // 64-row blocks (loaded together) per barrier pair.
-  auto fetch = [&](int q, int col) -> T {
-    T v = T(0);
+  auto fetch = [&](int q, int col) -> TC {
+    TC v = TC(0);
     if (q < Hc && col < bw) {
-      v = a.M.at(a.rm.row(c, q), a.pc + col);
-      if (a.rm.per_unit != 0 && (q % a.rm.per_unit) > col) v = T(0);
+      v = (TC)a.M.at(a.rm.row(c, q), a.pc + col);
+      if (a.rm.per_unit != 0 && (q % a.rm.per_unit) > col) v = TC(0);
     }
     return v;
   };
@@ -194,7 +199,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
     constexpr int CQB = C::CQB;
 #pragma unroll
     for (int i0 = 0; i0 < RPT; i0 += CQB) {
-      T tmp[CQB][EPT];
+      TC tmp[CQB][EPT];
 #pragma unroll
       for (int ib = 0; ib < CQB; ++ib)
 #pragma unroll
@@ -227,17 +232,17 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   // then, or nearly), lane i holding row i of T in registers, so T costs no
   // time of its own; wider tiles build T after the loop by recursive doubling.
   constexpr bool kTinLoop = TILE <= 32;
-  T trow[kTinLoop ? TILE : 1];
+  TC trow[kTinLoop ? TILE : 1];
 #pragma unroll
-  for (int k = 0; k < (kTinLoop ? TILE : 1); ++k) trow[k] = T(0);
+  for (int k = 0; k < (kTinLoop ? TILE : 1); ++k) trow[k] = TC(0);
   auto t_column = [&](int jj) {
     if constexpr (kTinLoop) {
-      const T tj = taus[jj];
-      T acc = T(0);
+      const TC tj = taus[jj];
+      TC acc = TC(0);
 #pragma unroll
       for (int k = 0; k < TILE; ++k)
         if (k < jj && k >= l) acc += trow[k] * Tl[k * LDT + jj];
-      const T val = l < jj ? -tj * acc : (l == jj ? tj : T(0));
+      const TC val = l < jj ? -tj * acc : (l == jj ? tj : TC(0));
 #pragma unroll
       for (int k = 0; k < TILE; ++k)
         if (k == jj) trow[k] = val;
@@ -246,7 +251,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   // ---- Householder loop over the panel columns ----
   for (int j = 0; j < kr; ++j) {
     const int ow = j / CPT, oc = j % CPT;
-    T* vb = vbuf + (j & 1) * C::HMAX;
+    TC* vb = vbuf + (j & 1) * C::HMAX;
     if (w == ow) {
       double sp[4] = {0.0, 0.0, 0.0, 0.0}, alpha_l = 0.0;
 #pragma unroll
@@ -274,28 +279,28 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
           if (cc != oc) continue;
-          T v = x[i][cc];
-          T vv;
-          if (q > j) { v = (T)((double)v * scal); vv = v; }
-          else if (q == j) { vv = T(1); v = (T)beta; }
-          else vv = T(0);
+          TC v = x[i][cc];
+          TC vv;
+          if (q > j) { v = (TC)((double)v * scal); vv = v; }
+          else if (q == j) { vv = TC(1); v = (TC)beta; }
+          else vv = TC(0);
           x[i][cc] = v;
           vb[q] = vv;
         }
       }
-      if (l == 0) { taus[j] = (T)tau; Tl[j * LDT + j] = (T)tau; }
+      if (l == 0) { taus[j] = (TC)tau; Tl[j * LDT + j] = (TC)tau; }
     }
     __syncthreads();
     if (kTinLoop && w == 0 && j >= 1) t_column(j - 1);
-    const T tau = taus[j];
+    const TC tau = taus[j];
     // v is kept in registers when the chunk leaves room for it, else re-read from LDS
-    constexpr bool kCacheV = RPT * ((int)sizeof(T) / 4) * (CPT + 1) <= 96;
-    T vr[kCacheV ? RPT : 1];
+    constexpr bool kCacheV = RPT * ((int)sizeof(TC) / 4) * (CPT + 1) <= 96;
+    TC vr[kCacheV ? RPT : 1];
     if constexpr (kCacheV) {
 #pragma unroll
       for (int i = 0; i < RPT; ++i) vr[i] = vb[i * 64 + l];
     }
-    auto vget = [&](int i) -> T {
+    auto vget = [&](int i) -> TC {
       if constexpr (kCacheV) return vr[i];
       else return vb[i * 64 + l];
     };
@@ -304,12 +309,12 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
       const int gc = w * CPT + cc;
       if (gc == j || gc >= bw) continue;
       // four independent partial sums shorten the dependent FMA chain
-      T dp[4] = {T(0), T(0), T(0), T(0)};
+      TC dp[4] = {TC(0), TC(0), TC(0), TC(0)};
 #pragma unroll
       for (int i = 0; i < RPT; ++i) dp[i & 3] += vget(i) * x[i][cc];
-      T d = wave_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
+      TC d = wave_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
       if (gc > j) {
-        const T td = tau * d;
+        const TC td = tau * d;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) x[i][cc] -= td * vget(i);
       } else if (l == 0) {
@@ -339,7 +344,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
     for (int t = threadIdx.x; t < npair * bs * bs; t += blockDim.x) {
       const int p = t / (bs * bs), r = (t / bs) % bs, cidx = t % bs;
       const int i0 = p * 2 * bs, ia = i0 + r, ib = i0 + bs + cidx;
-      T s = T(0);
+      TC s = TC(0);
       if (ib < kr) {
         for (int lq = i0 + bs; lq <= ib; ++lq) s += Tl[ia * LDT + lq] * Tl[lq * LDT + ib];
       }
@@ -351,7 +356,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
       const int p = t / (bs * bs), r = (t / bs) % bs, cidx = t % bs;
       const int i0 = p * 2 * bs, ia = i0 + r, ib = i0 + bs + cidx;
       if (ib < kr) {
-        T s = T(0);
+        TC s = TC(0);
         for (int lq = ia; lq < i0 + bs; ++lq) s += Tl[ia * LDT + lq] * Mtmp[p * bs * bs + (lq - i0) * bs + cidx];
         Tl[ia * LDT + ib] = -s;
       }
@@ -364,7 +369,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   T* Tout = a.Tm + (int64_t)c * TILE * TILE;
   for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
     const int r = t % TILE, col = t / TILE;
-    Tout[t] = (r < kr && col < kr && r <= col) ? Tl[r * LDT + col] : T(0);
+    Tout[t] = (r < kr && col < kr && r <= col) ? (T)Tl[r * LDT + col] : T(0);
   }
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
@@ -374,7 +379,7 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
     for (int i = 0; i < RPT; ++i) {
       const int q = i * 64 + l;
       if (q >= Hc) continue;
-      const T v = q > gc ? x[i][cc] : (q == gc ? T(1) : T(0));
+      const T v = q > gc ? (T)x[i][cc] : (q == gc ? T(1) : T(0));
       a.V[(row0 + q) + (int64_t)gc * a.ldv] = v;
     }
   }
@@ -386,15 +391,15 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int q = i * 64 + l;
-      if (q < kr && q <= gc) a.M.at(a.rm.row(c, q), a.pc + gc) = x[i][cc];
+      if (q < kr && q <= gc) a.M.at(a.rm.row(c, q), a.pc + gc) = (T)x[i][cc];
     }
   }
   PANEL_MARK(slot, 4);
 }
 
-template <typename T, int TILE, int RPT>
+template <typename T, int TILE, int RPT, typename TC>
 __global__ __launch_bounds__(1024) void k_chunk_qr(ChunkQRArgs<T> a) {
-  chunk_qr_body<T, TILE, RPT>(a, blockIdx.x);
+  chunk_qr_body<T, TILE, RPT, TC>(a, blockIdx.x);
 }
 
 // Batched form: one single-chunk panel per matrix, matrix blockIdx.x of the table.
@@ -412,21 +417,21 @@ __host__ __device__ inline int chunk_tier(int P, int64_t h) {
   return RPT;
 }
 
-template <typename T, int TILE, int RPT>
+template <typename T, int TILE, int RPT, typename TC>
 __global__ __launch_bounds__(1024) void k_chunk_qr_b(const ChunkQRArgs<T>* __restrict__ tab) {
   const ChunkQRArgs<T>& a = tab[blockIdx.x];
   switch (chunk_tier<RPT>(a.P, a.h)) {  // the same choice as a single call
     case 2:
-      if constexpr (RPT > 2) { chunk_qr_body<T, TILE, 2>(a, 0); return; }
+      if constexpr (RPT > 2) { chunk_qr_body<T, TILE, 2, TC>(a, 0); return; }
       break;
     case 8:
-      if constexpr (RPT > 8) { chunk_qr_body<T, TILE, 8>(a, 0); return; }
+      if constexpr (RPT > 8) { chunk_qr_body<T, TILE, 8, TC>(a, 0); return; }
       break;
     case 16:
-      if constexpr (RPT > 16) { chunk_qr_body<T, TILE, 16>(a, 0); return; }
+      if constexpr (RPT > 16) { chunk_qr_body<T, TILE, 16, TC>(a, 0); return; }
       break;
   }
-  chunk_qr_body<T, TILE, RPT>(a, 0);
+  chunk_qr_body<T, TILE, RPT, TC>(a, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,36 +528,39 @@ hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int tr
   return hipGetLastError();
 }
 
-template <typename T, int TILE, int RPT>
+template <typename TC, int TILE, int RPT>
 static size_t chunk_qr_lds() {
-  return sizeof(T) * (ChunkQRCfg<T, TILE, RPT>::CQB * 64 * (TILE + 1) + 2 * 64 * RPT + TILE + TILE * (TILE + 1));
+  return sizeof(TC) * (ChunkQRCfg<TC, TILE, RPT>::CQB * 64 * (TILE + 1) + 2 * 64 * RPT + TILE + TILE * (TILE + 1));
 }
 
-template <typename T, int TILE, int RPT>
+template <typename T, int TILE, int RPT, typename TC = T>
 static hipError_t launch_cqr(const ChunkQRArgs<T>& a, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && TILE > 64) {
+  if constexpr (sizeof(TC) == 8 && TILE > 64) {
     return hipErrorInvalidConfiguration;
   } else {
-  const size_t lds = chunk_qr_lds<T, TILE, RPT>();
-  static bool configured = false;
-  if (!configured) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr<T, TILE, RPT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    configured = true;
-  }
-  const int tier = chunk_tier<RPT>(a.P, a.h);
-  if constexpr (RPT > 2) {
-    if (tier == 2) return launch_cqr<T, TILE, 2>(a, st);
-  }
-  if constexpr (RPT > 8) {
-    if (tier == 8) return launch_cqr<T, TILE, 8>(a, st);
-  }
-  if constexpr (RPT > 16) {
-    if (tier == 16) return launch_cqr<T, TILE, 16>(a, st);
-  }
-  hipLaunchKernelGGL((k_chunk_qr<T, TILE, RPT>), dim3(a.P), dim3(1024), lds, st, a);
-  return hipGetLastError();
+    if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value) {
+      if (a.hp) return launch_cqr<T, TILE, RPT, double>(a, st);
+    }
+    const size_t lds = chunk_qr_lds<TC, TILE, RPT>();
+    static bool configured = false;
+    if (!configured) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr<T, TILE, RPT, TC>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      configured = true;
+    }
+    const int tier = chunk_tier<RPT>(a.P, a.h);
+    if constexpr (RPT > 2) {
+      if (tier == 2) return launch_cqr<T, TILE, 2, TC>(a, st);
+    }
+    if constexpr (RPT > 8) {
+      if (tier == 8) return launch_cqr<T, TILE, 8, TC>(a, st);
+    }
+    if constexpr (RPT > 16) {
+      if (tier == 16) return launch_cqr<T, TILE, 16, TC>(a, st);
+    }
+    hipLaunchKernelGGL((k_chunk_qr<T, TILE, RPT, TC>), dim3(a.P), dim3(1024), lds, st, a);
+    return hipGetLastError();
   }
 }
 
@@ -569,32 +577,35 @@ int chunk_qr_hmax(int tile) {
 template int chunk_qr_hmax<float>(int);
 template int chunk_qr_hmax<double>(int);
 
-template <typename T, int TILE, int RPT>
-static hipError_t launch_cqr_b(const ChunkQRArgs<T>* tab, int count, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && TILE > 64) {
+template <typename T, int TILE, int RPT, typename TC = T>
+static hipError_t launch_cqr_b(const ChunkQRArgs<T>* tab, int count, int hp, hipStream_t st) {
+  if constexpr (sizeof(TC) == 8 && TILE > 64) {
     return hipErrorInvalidConfiguration;
   } else {
-    const size_t lds = chunk_qr_lds<T, TILE, RPT>();
+    if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value) {
+      if (hp) return launch_cqr_b<T, TILE, RPT, double>(tab, count, hp, st);
+    }
+    const size_t lds = chunk_qr_lds<TC, TILE, RPT>();
     static bool configured = false;
     if (!configured) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr_b<T, TILE, RPT>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_chunk_qr_b<T, TILE, RPT, TC>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       configured = true;
     }
-    hipLaunchKernelGGL((k_chunk_qr_b<T, TILE, RPT>), dim3(count), dim3(1024), lds, st, tab);
+    hipLaunchKernelGGL((k_chunk_qr_b<T, TILE, RPT, TC>), dim3(count), dim3(1024), lds, st, tab);
     return hipGetLastError();
   }
 }
 
 template <typename T>
-hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, hipStream_t st) {
+hipError_t launch_chunk_qr_batched(int tile, const ChunkQRArgs<T>* tab, int count, int hp, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   switch (tile) {
-    case 16: return launch_cqr_b<T, 16, ChunkRPT<T, 16>::value>(tab, count, st);
-    case 32: return launch_cqr_b<T, 32, ChunkRPT<T, 32>::value>(tab, count, st);
-    case 64: return launch_cqr_b<T, 64, ChunkRPT<T, 64>::value>(tab, count, st);
-    case 128: return launch_cqr_b<T, 128, ChunkRPT<T, 128>::value>(tab, count, st);
+    case 16: return launch_cqr_b<T, 16, ChunkRPT<T, 16>::value>(tab, count, hp, st);
+    case 32: return launch_cqr_b<T, 32, ChunkRPT<T, 32>::value>(tab, count, hp, st);
+    case 64: return launch_cqr_b<T, 64, ChunkRPT<T, 64>::value>(tab, count, hp, st);
+    case 128: return launch_cqr_b<T, 128, ChunkRPT<T, 128>::value>(tab, count, hp, st);
   }
   return hipErrorInvalidValue;
 }
@@ -655,7 +666,7 @@ hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, d
   template hipError_t launch_stage_in<T>(const T*, int64_t, int64_t, int64_t, int, T*, int64_t, unsigned long long*, \
                                          int*, hipStream_t);                                                      \
   template hipError_t launch_chunk_qr<T>(int, const ChunkQRArgs<T>&, hipStream_t);                               \
-  template hipError_t launch_chunk_qr_batched<T>(int, const ChunkQRArgs<T>*, int, hipStream_t);                  \
+  template hipError_t launch_chunk_qr_batched<T>(int, const ChunkQRArgs<T>*, int, int, hipStream_t);             \
   template hipError_t launch_stage_in_batched<T>(const BatchMat<T>*, int, unsigned long long*, int64_t, hipStream_t); \
   template hipError_t launch_band_pack_batched<T>(const BatchMat<T>*, int, int, int64_t, hipStream_t);          \
   template hipError_t launch_band_pack<T>(const T*, int64_t, int64_t, int, double*, int64_t, const int*, int,     \

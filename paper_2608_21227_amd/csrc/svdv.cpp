@@ -117,9 +117,9 @@ int check_config_impl(int64_t m, int64_t n, int dtype, const svdv_config& c) {
   if (c.update_precision != 0 && c.update_precision != 2 && c.update_precision != 3)
     return fail(SVDV_ERR_UNSUPPORTED, "update_precision must be 0 (input precision), 2 (BF16) or 3 (FP16)");
   if (c.update_precision != 0 &&
-      (dtype != SVDV_F32 || !larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)))
-    return fail(SVDV_ERR_UNSUPPORTED, "BF16/FP16 trailing updates need float32 input and a configuration whose "
-                                      "strip fits in registers");
+      (dtype != SVDV_F32 || c.tile > 64 || !larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)))
+    return fail(SVDV_ERR_UNSUPPORTED, "BF16/FP16 trailing updates need float32 input, a tile of at most 64 (the "
+                                      "float64 panel must fit in LDS) and a configuration whose strip fits in registers");
   if (dtype == SVDV_F64 && c.tile > 64) return fail(SVDV_ERR_UNSUPPORTED, "float64 supports tiles up to 64");
   const bool ok = dtype == SVDV_F32 ? larfb_ok<float>(c.tile, c.threads, c.inner_block)
                                     : larfb_ok<double>(c.tile, c.threads, c.inner_block);
@@ -357,6 +357,7 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
     a.V = vws + lv.voff;
     a.ldv = lv.ldv;
     a.Tm = tws + lv.toff;
+    a.hp = cfg.update_precision != 0 ? 1 : 0;
     g_timing.kbegin(1, st);
     HIPCHK(launch_chunk_qr<T>(cfg.tile, a, st));
     // Householder QR of P chunks of (chunk rows x bw): 2 r bw^2 flops, panel read and written once
@@ -667,6 +668,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         a.V = Vp;
         a.ldv = (h + 15) / 16 * 16;
         a.Tm = Tp;
+        a.hp = cfg.update_precision != 0 ? 1 : 0;
         LarfbArgs<T>& u = uq[k * cnt + i];
         u.M = a.M;
         u.rm = a.rm;
@@ -705,6 +707,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
         a.V = Vp;
         a.ldv = (h + 15) / 16 * 16;
         a.Tm = Tp;
+        a.hp = cfg.update_precision != 0 ? 1 : 0;
         LarfbArgs<T>& u = ul[k * cnt + i];
         u.M = a.M;
         u.rm = a.rm;
@@ -784,6 +787,7 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
 
   // ---- the launch sequence ----
   const int nw = cfg.threads / 64, ib = cfg.inner_block, prec = cfg.update_precision;
+  const int hp = prec != 0 ? 1 : 0;  // panels in float64 arithmetic when the updates run in BF16/FP16
   ChaseArgs L{};
   L.b = b;
   L.W = W;
@@ -799,11 +803,11 @@ int batched_build(BatchPlan& P, const void* const* A_array, void* S) {
     const BatchMat<T>* dmats = (const BatchMat<T>*)(base + mats_off);
     HIPCHK(launch_stage_in_batched<T>(dmats, cnt, (unsigned long long*)(base + amax_off), maxM * maxN, st));
     for (int64_t k = 0; k < steps; ++k) {
-      HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + qr_off) + k * cnt, n_qr[k], st));
+      HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + qr_off) + k * cnt, n_qr[k], hp, st));
       HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_qr[k], (const LarfbArgs<T>*)(base + uq_off) + k * cnt,
                                      n_qr[k], mc_qr[k], lo_qr[k], hi_qr[k], st));
       if (n_lq[k] > 0) {
-        HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + lq_off) + k * cnt, n_lq[k], st));
+        HIPCHK(launch_chunk_qr_batched<T>(b, (const ChunkQRArgs<T>*)(base + lq_off) + k * cnt, n_lq[k], hp, st));
         HIPCHK(launch_larfb_batched<T>(b, nw, ib, prec, vec_lq[k], (const LarfbArgs<T>*)(base + ul_off) + k * cnt,
                                        n_lq[k], mc_lq[k], lo_lq[k], hi_lq[k], st));
       }

@@ -1,5 +1,6 @@
 """Reduced-precision trailing updates (BF16 / FP16 MFMA operands, float32
-accumulation; panels, stage 2 and stage 3 unchanged) against float64 references.
+accumulation; panel factorisation in float64 arithmetic, stage 2 and stage 3 in
+float64) against float64 references.
 
 Tolerances follow from the operand rounding: every operand of the two products
 of the update is rounded to a format with unit roundoff u (BF16 2^-8, FP16
@@ -7,9 +8,15 @@ of the update is rounded to a format with unit roundoff u (BF16 2^-8, FP16
 2u |V| |T| |V|^T |C| + 2u |V| |Z'| entrywise, i.e. in Frobenius norm by
 4 u ||V||_F^2 ||T||_F ||C||_F.  The whole reduction applies 2 n / b updates to
 a matrix of norm sigma_1; their perturbations add like a random walk, so the
-singular values move by about u sqrt(2 n / b) sigma_1 (times a small constant,
-taken as 8 below).
+singular values move by about u sqrt(2 n / b) sigma_1 (times a small constant).
+That is a bound for the worst case; the measured normwise errors of whole
+calls are far below it (about 0.08 u for BF16 and 0.06 u for FP16 at n = 8192,
+cond 1e4), so the end-to-end gates below are one unit roundoff of the low
+precision relative to sigma_1: an order of magnitude above what is measured,
+and far below what a wrong update (or one in the wrong precision) would give.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -76,6 +83,49 @@ def test_end_to_end_reduced_precision(prec):
     nw = np.max(np.abs(got - ref)) / ref[0]
     rel = np.max(np.abs(got - ref) / ref)
     print(f"[precision] {NAMES[prec]} n={n}: normwise {nw:.3e}, max relative {rel:.3e}", flush=True)
-    bound = 8 * U_LOW[prec] * np.sqrt(2 * n / b)
-    assert nw <= bound, f"{NAMES[prec]} normwise error {nw:.3e} > {bound:.3e}"
+    assert nw <= U_LOW[prec], f"{NAMES[prec]} normwise error {nw:.3e} > {U_LOW[prec]:.3e}"
     assert np.all(np.diff(got) <= 0) and np.all(got >= 0)
+
+
+# ----------------------------------------------------------------------------- mixed-precision workload
+# n = 8192, A = U diag(s) V^T with s geometric from 1 to 1e-4 (cond 1e4), stored in
+# float32; the stored float64 oracle values of exactly that rounded matrix
+# (tests/golden/cfg3_n8192_float32.npy, written by tests/golden/make_golden.py).
+# Tile 16 with the 1024-thread update: the panels run their multi-chunk tree
+# (8192 rows, 2048 per chunk) and the 16-wave register strip of the update.
+GOLDEN_CFG3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_n8192_float32.npy")
+
+
+@pytest.fixture(scope="module")
+def cfg3_case():
+    if not os.path.exists(GOLDEN_CFG3):
+        pytest.skip("cfg3 golden values not written")
+    torch = torch_cuda()
+    a = workloads.cfg3_matrix(8192, "float32")
+    dev = torch.from_numpy(np.ascontiguousarray(a.T)).t().cuda()
+    del a
+    return dev, np.load(GOLDEN_CFG3)
+
+
+@pytest.mark.parametrize("prec", [0, 2, 3])
+def test_mixed_precision_workload_against_oracle(cfg3_case, prec):
+    torch = torch_cuda()
+    svdv = _svdv()
+    dev, ref = cfg3_case
+    cfg = svdv.Config(tile=16, threads=1024, inner_block=1, sweep_width=4, update_precision=prec)
+    name = NAMES.get(prec, "fp32")
+    banner(f"mixed-precision workload n=8192 cond 1e4, {name} updates")
+    s = svdv.svd_values(dev, config=cfg)
+    torch.cuda.synchronize()
+    got = s.cpu().numpy().astype(np.float64)
+    nw = float(np.max(np.abs(got - ref)) / ref[0])
+    rel = float(np.max(np.abs(got - ref) / ref))
+    print(f"[precision] {name} n=8192 cond 1e4: normwise {nw:.3e}, max relative {rel:.3e}", flush=True)
+    assert np.all(np.isfinite(got)) and np.all(np.diff(got) <= 0)
+    if prec == 0:
+        from gpu_util import gate
+        gate("float32", got, ref)
+    else:
+        assert nw <= U_LOW[prec], f"{name} normwise error {nw:.3e} > {U_LOW[prec]:.3e}"
+        # the reduced precision is really in use: well above float32 rounding
+        assert nw > 16 * 2.0 ** -24, f"{name} error {nw:.3e} is at float32 level"
