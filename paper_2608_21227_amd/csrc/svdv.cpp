@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/svdv.h"
@@ -553,7 +554,18 @@ struct BatchPlan {
     mem = nullptr;
   }
 };
-std::map<std::pair<int, void*>, BatchPlan> g_batch;
+// Cached batched plans, one per (device, stream, configuration): a batch whose
+// matrices take different configurations keeps one plan per configuration.
+struct BatchKey {
+  int dev;
+  void* stream;
+  int32_t tile, threads, inner_block, sweep_width, precision;
+  bool operator<(const BatchKey& o) const {
+    return std::tie(dev, stream, tile, threads, inner_block, sweep_width, precision) <
+           std::tie(o.dev, o.stream, o.tile, o.threads, o.inner_block, o.sweep_width, o.precision);
+  }
+};
+std::map<BatchKey, BatchPlan> g_batch;
 
 // Builds the plan's tables and workspaces (uploaded here, before any capture)
 // and the recorder of its launch sequence.
@@ -1103,22 +1115,43 @@ int svdv_apply_qt(const void* V, int64_t ldv, const void* Tm, int64_t ldt, void*
   return run((double*)C, (const double*)V, (const double*)Tm);
 }
 
-int svd_values_batched(const void* const* A_array, const int64_t* m, const int64_t* n, const int64_t* lda, int64_t batch,
-                       int32_t dtype, void* S, const int64_t* S_offset, void* stream, const svdv_config* cfg) {
-  if (batch < 0) return fail(SVDV_ERR_INVALID_ARG, "batch must be >= 0");
-  if (batch == 0) return SVDV_OK;
-  if (batch > (1 << 20)) return fail(SVDV_ERR_UNSUPPORTED, "batch above 2^20");
-  if (!A_array || !m || !n || !lda || !S_offset || !S) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
-  int64_t maxdim = 1;
-  for (int64_t i = 0; i < batch; ++i) {
-    int rc = check_matrix_args(A_array[i], m[i], n[i], lda[i], dtype);
-    if (rc) return rc;
-    if (S_offset[i] < 0) return fail(SVDV_ERR_INVALID_ARG, "negative S_offset");
-    maxdim = std::max<int64_t>(maxdim, std::max(m[i], n[i]));
+}  // extern "C"
+
+namespace {
+
+// Streams (default priority, non-blocking) and events of the concurrent groups of a
+// batch, created once per device and kept until the process ends.
+int group_streams(int count, std::vector<hipStream_t>& out) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<hipStream_t>& v = pool[dev];
+  while ((int)v.size() < count) {
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    v.push_back(s);
   }
-  svdv_config c = cfg ? *cfg : default_config(maxdim, maxdim, dtype);
-  int rc = check_config_impl(maxdim, maxdim, dtype, c);
-  if (rc) return rc;
+  out.assign(v.begin(), v.begin() + count);
+  return SVDV_OK;
+}
+int group_event(int i, hipEvent_t* out) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, hipEvent_t> pool;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  hipEvent_t& e = pool[{dev, i}];
+  if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  *out = e;
+  return SVDV_OK;
+}
+
+// One batch (or one group of a batch) under one configuration.
+int batched_with_config(const void* const* A_array, const int64_t* m, const int64_t* n, const int64_t* lda,
+                        int64_t batch, int32_t dtype, void* S, const int64_t* S_offset, void* stream,
+                        const svdv_config& c, int64_t maxdim) {
   const bool reg_ok = dtype == SVDV_F32 ? larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
                                         : larfb_reg_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
   const int hmax = dtype == SVDV_F32 ? chunk_qr_hmax<float>(c.tile) : chunk_qr_hmax<double>(c.tile);
@@ -1127,7 +1160,7 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
     // matrices taller than one panel chunk): the matrices run one after another
     const int es = elem_size(dtype);
     for (int64_t i = 0; i < batch; ++i) {
-      rc = svd_values_ex(A_array[i], m[i], n[i], lda[i], dtype, (char*)S + S_offset[i] * es, stream, &c);
+      const int rc = svd_values_ex(A_array[i], m[i], n[i], lda[i], dtype, (char*)S + S_offset[i] * es, stream, &c);
       if (rc) return rc;
     }
     return SVDV_OK;
@@ -1135,7 +1168,7 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
-  BatchPlan& P = g_batch[{dev, stream}];
+  BatchPlan& P = g_batch[BatchKey{dev, stream, c.tile, c.threads, c.inner_block, c.sweep_width, c.update_precision}];
   const std::vector<int64_t> mv(m, m + batch), nv(n, n + batch), lv(lda, lda + batch), ov(S_offset, S_offset + batch);
   const bool same = P.exec && P.dtype == dtype && std::memcmp(&P.cfg, &c, sizeof(c)) == 0 && P.m == mv && P.n == nv &&
                     P.lda == lv && P.soff == ov;
@@ -1160,6 +1193,101 @@ int svd_values_batched(const void* const* A_array, const int64_t* m, const int64
   hipStream_t st = (hipStream_t)stream;
   if (dtype == SVDV_F32) return batched_run<float>(P, A_array, S, st);
   return batched_run<double>(P, A_array, S, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int svd_values_batched(const void* const* A_array, const int64_t* m, const int64_t* n, const int64_t* lda, int64_t batch,
+                       int32_t dtype, void* S, const int64_t* S_offset, void* stream, const svdv_config* cfg) {
+  if (batch < 0) return fail(SVDV_ERR_INVALID_ARG, "batch must be >= 0");
+  if (batch == 0) return SVDV_OK;
+  if (batch > (1 << 20)) return fail(SVDV_ERR_UNSUPPORTED, "batch above 2^20");
+  if (!A_array || !m || !n || !lda || !S_offset || !S) return fail(SVDV_ERR_INVALID_ARG, "NULL pointer");
+  int64_t maxdim = 1;
+  for (int64_t i = 0; i < batch; ++i) {
+    int rc = check_matrix_args(A_array[i], m[i], n[i], lda[i], dtype);
+    if (rc) return rc;
+    if (S_offset[i] < 0) return fail(SVDV_ERR_INVALID_ARG, "negative S_offset");
+    maxdim = std::max<int64_t>(maxdim, std::max(m[i], n[i]));
+  }
+  if (cfg) {
+    const int rc = check_config_impl(maxdim, maxdim, dtype, *cfg);
+    if (rc) return rc;
+    return batched_with_config(A_array, m, n, lda, batch, dtype, S, S_offset, stream, *cfg, maxdim);
+  }
+  // per-size tuned defaults: the matrices are grouped by the configuration the tuned
+  // table gives their size, and each group runs as one batch (in order of first appearance)
+  std::vector<svdv_config> cfgs;
+  std::vector<std::vector<int64_t>> members;
+  for (int64_t i = 0; i < batch; ++i) {
+    svdv_config c = default_config(m[i], n[i], dtype);
+    // a group runs in the batched kernels only with a register-strip update: keep the
+    // tuned tile and sweep width, and take the widest such workgroup otherwise
+    const bool reg = dtype == SVDV_F32 ? larfb_reg_valid<float>(c.tile / 16, c.inner_block, c.threads / 64)
+                                       : larfb_reg_valid<double>(c.tile / 16, c.inner_block, c.threads / 64);
+    if (!reg) {
+      for (int th : {1024, 512, 256, 128}) {
+        const bool ok = dtype == SVDV_F32 ? larfb_reg_valid<float>(c.tile / 16, 1, th / 64)
+                                          : larfb_reg_valid<double>(c.tile / 16, 1, th / 64);
+        if (ok) {
+          c.threads = th;
+          c.inner_block = 1;
+          break;
+        }
+      }
+    }
+    size_t g = 0;
+    while (g < cfgs.size() && std::memcmp(&cfgs[g], &c, sizeof(c)) != 0) ++g;
+    if (g == cfgs.size()) {
+      cfgs.push_back(c);
+      members.emplace_back();
+    }
+    members[g].push_back(i);
+  }
+  // groups run concurrently: each on a stream of its own, forked from and joined
+  // back to the caller's stream (one group runs on the caller's stream itself)
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<hipStream_t> gst(cfgs.size(), st);
+  if (cfgs.size() > 1) {
+    int rc = group_streams((int)cfgs.size(), gst);
+    if (rc) return rc;
+    hipEvent_t fork = nullptr;
+    rc = group_event(0, &fork);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(fork, st));
+    for (size_t g = 0; g < cfgs.size(); ++g) HIPCHK(hipStreamWaitEvent(gst[g], fork, 0));
+  }
+  for (size_t g = 0; g < cfgs.size(); ++g) {
+    const std::vector<int64_t>& ix = members[g];
+    std::vector<const void*> a(ix.size());
+    std::vector<int64_t> mm(ix.size()), nn(ix.size()), ll(ix.size()), oo(ix.size());
+    int64_t gmax = 1;
+    for (size_t q = 0; q < ix.size(); ++q) {
+      a[q] = A_array[ix[q]];
+      mm[q] = m[ix[q]];
+      nn[q] = n[ix[q]];
+      ll[q] = lda[ix[q]];
+      oo[q] = S_offset[ix[q]];
+      gmax = std::max<int64_t>(gmax, std::max(mm[q], nn[q]));
+    }
+    int rc = check_config_impl(gmax, gmax, dtype, cfgs[g]);
+    if (rc) return rc;
+    rc = batched_with_config(a.data(), mm.data(), nn.data(), ll.data(), (int64_t)ix.size(), dtype, S, oo.data(),
+                             (void*)gst[g], cfgs[g], gmax);
+    if (rc) return rc;
+  }
+  if (cfgs.size() > 1) {
+    for (size_t g = 0; g < cfgs.size(); ++g) {
+      hipEvent_t join = nullptr;
+      int rc = group_event(1 + (int)g, &join);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(join, gst[g]));
+      HIPCHK(hipStreamWaitEvent(st, join, 0));
+    }
+  }
+  return SVDV_OK;
 }
 
 int svdv_timing(int enable) {
@@ -1225,8 +1353,8 @@ int svdv_release(void) {
   }
   g_ws.clear();
   for (auto& kv : g_batch) {
-    hipSetDevice(kv.first.first);
-    hipStreamSynchronize((hipStream_t)kv.first.second);
+    hipSetDevice(kv.first.dev);
+    hipStreamSynchronize((hipStream_t)kv.first.stream);
     kv.second.release();
   }
   g_batch.clear();

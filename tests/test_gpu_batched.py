@@ -1,6 +1,8 @@
 """Batched singular values: every stage runs once for the whole batch (per-matrix
 argument tables), captured in a hipGraph and replayed; each matrix checked
 against the float64 oracle with the single-matrix gates."""
+import os
+
 import numpy as np
 import pytest
 
@@ -95,3 +97,51 @@ def test_batched_fallback_configuration():
     packed, offs = svdv.svd_values_batched(devs, config=cfg)
     torch.cuda.synchronize()
     _check(mats, packed, offs, "float32")
+
+
+def test_batched_default_uses_each_matrix_tuned_configuration_bitwise():
+    """Without a configuration the batch is grouped by the tuned configuration of
+    each matrix's size; every matrix then equals a single call with its default."""
+    torch = torch_cuda()
+    svdv = _svdv()
+    mats = _batch(12, 8, 300, "float32", seed=13)
+    devs = [torch.from_numpy(np.ascontiguousarray(a.T)).t().cuda() for a in mats]
+    banner("batched default configurations vs single calls, float32")
+    packed, offs = svdv.svd_values_batched(devs)
+    singles = [svdv.svd_values(d) for d in devs]
+    torch.cuda.synchronize()
+    got = packed.cpu().numpy()
+    for s1, off in zip(singles, offs):
+        s1 = s1.cpu().numpy()
+        assert np.array_equal(got[off:off + s1.size], s1)
+
+
+GOLDEN_CFG2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_b512_float32.npy")
+
+
+def test_batched_workload_against_oracle_values():
+    """The batched workload: 512 float32 matrices, n uniform in [32, 512], log-uniform
+    spectra in [1e-4, 1]; every matrix against the stored float64 oracle values of
+    exactly its rounded matrix (tests/golden/cfg2_b512_float32.npy), with the
+    single-matrix gates."""
+    if not os.path.exists(GOLDEN_CFG2):
+        pytest.skip("cfg2 golden values not written")
+    torch = torch_cuda()
+    svdv = _svdv()
+    mats, _ = workloads.cfg2_batch(512, 32, 512, "float32")
+    ref_all = np.load(GOLDEN_CFG2)
+    devs = [torch.from_numpy(np.ascontiguousarray(a.T)).t().cuda() for a in mats]
+    banner("batched workload 512 x float32 n in [32, 512] vs oracle")
+    packed, offs = svdv.svd_values_batched(devs)
+    torch.cuda.synchronize()
+    got = packed.cpu().numpy().astype(np.float64)
+    assert ref_all.size == sum(min(a.shape) for a in mats)
+    worst = 0.0
+    pos = 0
+    for a, off in zip(mats, offs):
+        k = min(a.shape)
+        ref = ref_all[pos:pos + k]
+        pos += k
+        nw, _ = gate("float32", got[off:off + k], ref)
+        worst = max(worst, nw)
+    print(f"[batched] 512 matrices: worst normwise error vs oracle {worst:.3e}", flush=True)
