@@ -101,15 +101,36 @@ def traffic_for(kind: str, cfg):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(a_np: np.ndarray, n: int, sweeps_total: int):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(a_np: np.ndarray, n: int, dtype: str):
+    """The float64 Jacobi oracle on this host's cores, on a bounded sample of the headline
+    workload: one sweep of the same matrix, scaled by the number of sweeps the oracle takes
+    to converge on it (recorded beside the stored oracle values when they were computed)."""
     import oracle
+    info_path = os.path.join(ROOT, "tests", "golden", f"cfg1_n{n}_{dtype}.json")
+    if os.path.exists(info_path):
+        with open(info_path) as f:
+            sweeps_total, src = int(json.load(f)["sweeps"]), "recorded when the stored oracle values were computed"
+    else:
+        sweeps_total, src = 18, "assumed (no record for this matrix)"
     threads = os.cpu_count() or 1
     secs, done = oracle.time_sweeps(a_np, 1, threads=threads)
     est = secs * sweeps_total
     gflops = (4.0 / 3.0) * n ** 3 / est / 1e9
     return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 of the {sweeps_total} Jacobi sweeps the oracle needs on this n={n} matrix "
-                      f"({secs:.1f} s, float64, OpenMP), extrapolated x{sweeps_total}"}
+            "sample": f"1 of the {sweeps_total} Jacobi sweeps the oracle needs on this n={n} {dtype} matrix "
+                      f"(sweep count {src}): {secs:.1f} s, float64, OpenMP on {threads} threads of "
+                      f"{_cpu_model()}; whole-run estimate {est:.0f} s"}
 
 
 def batched_report(torch, count: int = 512, reps: int = 5):
@@ -355,7 +376,7 @@ def main():
     }
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(a_np, n, 18)
+        out["cpu_baseline"] = cpu_baseline(a_np, n, dtype)
     if not args.no_extras:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         out["batched"] = batched_report(torch)

@@ -24,6 +24,16 @@ def path_for(name: str) -> str:
     return os.path.join(HERE, name + ".npy")
 
 
+def write_info(name: str, info: dict, secs: float, threads: int) -> None:
+    """Sidecar record of the oracle run that wrote `name` (Jacobi sweeps to convergence,
+    wall time and threads of this machine), read by the bench's CPU baseline."""
+    import json
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump({"sweeps": int(info["sweeps"]), "seconds": round(secs, 2), "threads": int(threads or os.cpu_count()),
+                   "offmax": float(info["offmax"])}, f)
+        f.write("\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="*", default=[1024, 2048, 4096])
@@ -33,11 +43,23 @@ def main():
                     help="also the batch of 512 float32 matrices (n uniform in [32, 512]): one packed array of "
                          "every matrix's values in batch order")
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--info", nargs="*", default=[],
+                    help="re-run the oracle on these stored workloads (e.g. cfg1_n4096_float32) only to record their "
+                         "sweep counts; the stored values are left as they are")
     args = ap.parse_args()
     jobs = [(f"cfg1_n{n}_{dt}", lambda n=n, dt=dt: workloads.cfg1_matrix(n, dt))
             for n in args.sizes for dt in args.dtypes]
     if args.cfg3:
         jobs.append(("cfg3_n8192_float32", lambda: workloads.cfg3_matrix(8192, "float32")))
+    for name in args.info:
+        _, nn, dt = name.split("_")
+        a = workloads.cfg1_matrix(int(nn[1:]), dt)
+        t = time.time()
+        info = {}
+        s = oracle.svd_values(a, threads=args.threads, info=info)
+        ok = np.array_equal(s, np.load(path_for(name)))
+        write_info(name, info, time.time() - t, args.threads)
+        print(f"{name}: sweeps={info['sweeps']} in {time.time() - t:.1f}s, same values as stored: {ok}", flush=True)
     if args.cfg2:
         out = path_for("cfg2_b512_float32")
         if os.path.exists(out):
@@ -58,6 +80,7 @@ def main():
         info = {}
         s = oracle.svd_values(a, threads=args.threads, info=info)
         np.save(out, s)
+        write_info(name, info, time.time() - t, args.threads)
         print(f"{name}: {time.time() - t:.1f}s sweeps={info['sweeps']}", flush=True)
 
 
