@@ -835,7 +835,12 @@ constexpr int kFlowLoaders = 2;  // ML
 constexpr int kFlowStorers = 2;  // MS
 constexpr int kFlowSlack = 2;  // K: extra ring rows (in units of b) between storing and refilling a slot
 constexpr int kFlowMaxW = 8;
-constexpr int kFlowNarrowW = 4;  // widths up to this run an instantiation with 256 VGPRs per lane
+// Instantiations by width.  A workgroup of at most 8 waves (two per SIMD) may use
+// 256 VGPRs per lane, which the task needs without spilling; 12 waves allow 168
+// and spill.  So widths up to 4 run with two loaders and two storers, widths 5
+// and 6 with one of each (8 waves), and only 7 and 8 with 12 waves.
+constexpr int kFlowNarrowW = 4;
+constexpr int kFlowMidW = 6;
 
 __host__ __device__ inline int flow_rows(int b, int W) { return (2 * W + 3 + kFlowSlack) * b; }
 
@@ -1182,15 +1187,17 @@ static bool use_pipe(int b, int W) { return b == 16 && W <= kFlowMaxW && chase_f
 static bool use_window(int b, int W) { return b == 32 && chase_win_lds_bytes(b, W) <= 159 * 1024; }
 
 static const void* chase_fn(int b, int W) {
-  if (use_pipe(b, W))
-    return W <= kFlowNarrowW ? (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>
-                             : (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>;
+  if (use_pipe(b, W)) {
+    if (W <= kFlowNarrowW) return (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>;
+    if (W <= kFlowMidW) return (const void*)k_chase_flow<16, 1, 1, kFlowSlack, kFlowMidW>;
+    return (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>;
+  }
   if (use_window(b, W)) return (const void*)k_chase_win<32>;
   return (const void*)k_chase;
 }
 
 static int chase_threads(int b, int W) {
-  if (use_pipe(b, W)) return 64 * (W + kFlowLoaders + kFlowStorers);
+  if (use_pipe(b, W)) return 64 * (W + (W > kFlowNarrowW && W <= kFlowMidW ? 2 : kFlowLoaders + kFlowStorers));
   return use_window(b, W) ? 64 * (W > WinGeom<32>::MIN_WAVES ? W : WinGeom<32>::MIN_WAVES) : 64 * W;
 }
 
@@ -1225,6 +1232,8 @@ static hipError_t launch_chase_kernel(const ChaseArgs& a, int grid, hipStream_t 
     if (fn == (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>)
       hipLaunchKernelGGL((k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowNarrowW>), dim3(grid), block,
                          lds, st, a);
+    else if (fn == (const void*)k_chase_flow<16, 1, 1, kFlowSlack, kFlowMidW>)
+      hipLaunchKernelGGL((k_chase_flow<16, 1, 1, kFlowSlack, kFlowMidW>), dim3(grid), block, lds, st, a);
     else if (fn == (const void*)k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>)
       hipLaunchKernelGGL((k_chase_flow<16, kFlowLoaders, kFlowStorers, kFlowSlack, kFlowMaxW>), dim3(grid), block, lds,
                          st, a);

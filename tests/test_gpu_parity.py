@@ -160,7 +160,7 @@ def test_stage_bidiag_matches_oracle(n, b):
     d_ref, e_ref = oracle.bulge_chase(band_dense, b)
     scale = np.linalg.norm(band_dense)
     results = []
-    for W in (1, 2, 3, 8):
+    for W in (1, 2, 3, 4, 5, 6, 8):
         # the chase alone needs only its own LDS to fit for (b, W): the library
         # reports any other width as unsupported, which skips that width
         cfg = svdv.Config(tile=b, sweep_width=W)
