@@ -343,6 +343,14 @@ def main():
                         "launches_per_step": v["launches"], "kernel": v["kernel"]}
     roofline = dict(rooflines[dom])
     roofline["traffic"] = traffic_for(dom, tuned)
+    # HBM bytes per launch from the committed counters (when taken for this kernel
+    # source and configuration) over the launch time measured here
+    for k, v in kinds.items():
+        tb = traffic_for(k, tuned)
+        if tb:
+            rooflines[k]["hbm_GBs_from_counters"] = round(tb / (v["ms"] * 1e-3 / v["launches"]) / 1e9, 3)
+            if k == dom:
+                roofline["hbm_GBs_from_counters"] = rooflines[k]["hbm_GBs_from_counters"]
     t_stage1 = stages.get("stage1", float("nan")) * 1e-3
     s1_flops = 8.0 / 3.0 * n ** 3
 
