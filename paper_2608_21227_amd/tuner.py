@@ -199,6 +199,7 @@ def main(argv=None) -> None:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--time-budget", type=float, default=0.0, help="stop measuring after this many seconds")
     ap.add_argument("--slow-ms", type=float, default=500.0)
+    ap.add_argument("--tiles", default=None, help="comma-separated tile sizes to search (default: all)")
     args = ap.parse_args(argv)
     n, dtype = args.n, args.dtype
     db = args.db or os.path.join(_HERE, "tuning", f"tuning_{n}_{dtype}.jsonl")
@@ -207,7 +208,8 @@ def main(argv=None) -> None:
     a_np = rng.standard_normal((n, n)).astype(dtype)
     a = torch.from_numpy(np.ascontiguousarray(a_np.T)).t().cuda()
     t0 = time.time()
-    cfgs = space()
+    tiles = tuple(int(x) for x in args.tiles.split(",")) if args.tiles else TILES
+    cfgs = space(tiles=tiles)
     order = np.random.default_rng(args.seed).permutation(len(cfgs))  # interleave so a partial run is a fair sample
     cfgs = [cfgs[i] for i in order]
 
@@ -234,6 +236,8 @@ def main(argv=None) -> None:
         table = load_table(args.table)
         table[f"{n}_{dtype}"] = {k: summ[k] for k in ("best", "best_ms", "median", "median_ms", "valid", "invalid",
                                                       "ratio_median_over_best", "plain_ms")}
+        if tiles != TILES:
+            table[f"{n}_{dtype}"]["tiles"] = list(tiles)
         save_table(table, args.table)
 
 
