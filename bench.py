@@ -82,9 +82,10 @@ def stage_breakdown(a, cfg, reps: int, torch):
     return {k: float(np.median(v)) for k, v in acc.items()}, kstats
 
 
-def traffic_for(kind: str, cfg):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken for this kernel class and configuration with the current kernel source."""
+def counters_for(kind: str, cfg, field: str):
+    """A figure from the committed rocprofv3 counter summaries (profiles/traffic.json),
+    if they were taken for this kernel class and configuration with the current
+    kernel source: HBM bytes per launch, or the MFMA busy fraction."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -98,7 +99,12 @@ def traffic_for(kind: str, cfg):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != e.get("source_sha256"):
             return None  # the kernel changed since the counters were taken
-    return e.get("bytes_per_launch")
+    return e.get(field)
+
+
+def traffic_for(kind: str, cfg):
+    """HBM bytes per launch from the committed counters (see counters_for)."""
+    return counters_for(kind, cfg, "bytes_per_launch")
 
 
 def _cpu_model() -> str:
@@ -351,6 +357,9 @@ def main():
             rooflines[k]["hbm_GBs_from_counters"] = round(tb / (v["ms"] * 1e-3 / v["launches"]) / 1e9, 3)
             if k == dom:
                 roofline["hbm_GBs_from_counters"] = rooflines[k]["hbm_GBs_from_counters"]
+        busy = counters_for(k, tuned, "mfma_busy")
+        if busy is not None:
+            rooflines[k]["mfma_busy_from_counters"] = busy
     t_stage1 = stages.get("stage1", float("nan")) * 1e-3
     s1_flops = 8.0 / 3.0 * n ** 3
 
