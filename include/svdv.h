@@ -80,7 +80,9 @@ typedef struct {
  * Singular values of the m x n matrix A (dtype SVDV_F32 or SVDV_F64), written
  * to S[0 .. min(m,n)-1] in A's dtype, descending and non-negative.
  * m == 0 or n == 0: returns SVDV_OK and writes nothing.
- * Non-finite input propagates NaN into S (no check on this path).
+ * An A holding a NaN or an infinity has no singular values: every entry of S
+ * is NaN after the stream completes (the staging pass that finds max|a| marks
+ * the input, and the stage that writes S reads the mark).
  * The tuned default configuration for (m, n, dtype) is used: the auto-tuner's
  * measured best (Eq. 1's argmin) of the cell of the same dtype nearest to
  * min(m, n) on a log scale, compiled into the library from its tuned table
@@ -121,6 +123,8 @@ int64_t svdv_noalloc_capacity(void);
  *   S         device buffer; matrix i writes min(m[i], n[i]) values at
  *             S + S_offset[i] elements (S_offset: HOST array [batch]).
  *   cfg       NULL: per-size tuned defaults; otherwise one config for all.
+ * A matrix holding a NaN or an infinity gets NaN values; the other matrices
+ * of the batch are not affected.
  * The whole batch is one stream-ordered sequence of persistent launches over
  * all matrices at once, captured in a hipGraph and replayed on later calls
  * with the same shapes.
@@ -144,7 +148,8 @@ int svdv_check_config(int64_t m, int64_t n, int32_t dtype, const svdv_config* cf
  *   (n' = min(m, n)) as float64 into `band`, row i at band + i * ldband,
  *   band[i * ldband + d] = B(i, i + d) for d = 0 .. TS (entries past column
  *   n'-1 are zero).  ldband >= TS + 1.  Values are unscaled (the internal
- *   power-of-two scaling is undone exactly).
+ *   power-of-two scaling is undone exactly).  An A holding a NaN or an
+ *   infinity gives a band of NaN.
  */
 int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dtype, double* band, int64_t ldband,
                     void* stream, const svdv_config* cfg);
@@ -155,8 +160,9 @@ int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dt
  * d[0..n-1] (diagonal) and e[0..n-2] (superdiagonal), float64.  Signs of d, e
  * are not normalised.  cfg->sweep_width selects the schedule; the result is
  * bitwise identical for every sweep_width.  b must be one of the tile sizes.
- * If a bounded wait between the chase's workgroups gives up (it never does in
- * a correct launch), every entry of d and e is NaN after the stream completes.
+ * If the band holds a NaN or an infinity, or a bounded wait between the
+ * chase's workgroups gives up (it never does in a correct launch), every entry
+ * of d and e is NaN after the stream completes.
  */
 int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, double* d, double* e, void* stream,
                       const svdv_config* cfg);
@@ -166,7 +172,8 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
  * (float64, n and n-1 entries), written descending to S in out_dtype.  Each
  * value is located by Sturm-count multisection in float64 to an absolute
  * width of 4u (max|d| + max|e|) for SVDV_F64 output and 2^-32 (max|d| + max|e|)
- * for SVDV_F32 output, then rounded to out_dtype.
+ * for SVDV_F32 output, then rounded to out_dtype.  If d or e holds a NaN or an
+ * infinity, every value is NaN.
  */
 int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_dtype, void* S, void* stream);
 

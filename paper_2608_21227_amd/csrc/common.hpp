@@ -9,6 +9,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
+// Scale exponent recorded for an input that holds a NaN or an infinity: no
+// finite maximum has a binary exponent anywhere near it.  Every output stage
+// that reads the exponent then writes NaN (the input has no singular values).
+constexpr int kExpNonFinite = -(1 << 30);
 
 // Strided matrix view: element (r, c) lives at p[r * rs + c * cs].
 // QR sweeps use the column-major matrix as is (rs = 1, cs = ld); LQ sweeps use

@@ -153,7 +153,8 @@ hipError_t launch_band_pack(const T* W, int64_t ldw, int64_t n, int b, double* B
 template <typename T>
 hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double* out, int64_t ldo, const int* exp_in,
                                hipStream_t st);
-hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, hipStream_t st);
+hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, int* nonfinite,
+                              hipStream_t st);
 
 // Stage 2.
 struct ChaseArgs {

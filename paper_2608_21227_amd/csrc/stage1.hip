@@ -76,7 +76,7 @@ __device__ __forceinline__ void absmax_body(const T* __restrict__ A, int64_t m, 
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = idx / m, i = idx - j * m;
     double v = fabs((double)A[i + j * lda]);
-    if (!(v <= mx)) mx = v;  // NaN wins
+    if (v != v || v > mx) mx = v;  // a NaN, once met, stays (no comparison replaces it)
   }
   unsigned long long b = abs_bits(mx);
   for (int off = 32; off > 0; off >>= 1) {
@@ -110,7 +110,10 @@ __device__ __forceinline__ void copy_scale_body(const T* __restrict__ A, int64_t
                                                 int transpose, T* __restrict__ W, int64_t ldw,
                                                 const unsigned long long* amax, int* exp_out) {
   int e = scale_exponent(*amax);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double mx = __longlong_as_double((long long)*amax);
+    *exp_out = isfinite(mx) ? e : kExpNonFinite;  // the data is copied unscaled either way
+  }
   // W is M x N with M = transpose ? n : m
   int64_t M = transpose ? n : m, N = transpose ? m : n;
   int64_t total = M * N;
@@ -488,23 +491,30 @@ __global__ void k_band_extract(const T* __restrict__ W, int64_t ldw, int64_t n, 
                                int64_t ldo, const int* exp_in) {
   const int64_t total = n * (b + 1);
   const int e = *exp_in;
+  const bool nonfinite = e == kExpNonFinite;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / (b + 1);
     const int d = (int)(idx - i * (b + 1));
     const int64_t j = i + d;
-    out[i * ldo + d] = j < n ? ldexp((double)W[i + j * ldw], e) : 0.0;
+    out[i * ldo + d] = nonfinite ? __builtin_nan("") : (j < n ? ldexp((double)W[i + j * ldw], e) : 0.0);
   }
 }
 
+// A NaN or an infinity among the band's entries sets *nonfinite (the chase then
+// gives up at once and its d and e are written as NaN).
 __global__ void k_band_import(const double* __restrict__ in, int64_t ldi, int64_t n, int b, double* __restrict__ Bs,
-                              int64_t ldb) {
+                              int64_t ldb, int* nonfinite) {
   const int64_t total = n * ldb;
+  bool bad = false;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / ldb;
     const int d = (int)(idx - i * ldb);
     const int64_t off = d - (b - 1);
-    Bs[idx] = (off >= 0 && off <= b && i + off < n) ? in[i * ldi + off] : 0.0;
+    const double v = (off >= 0 && off <= b && i + off < n) ? in[i * ldi + off] : 0.0;
+    bad = bad || !isfinite(v);
+    Bs[idx] = v;
   }
+  if (bad) __hip_atomic_store(nonfinite, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,8 +667,9 @@ hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double
   return hipGetLastError();
 }
 
-hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, hipStream_t st) {
-  hipLaunchKernelGGL(k_band_import, dim3(grid_for(n * ldb, 256)), dim3(256), 0, st, in, ldi, n, b, Bs, ldb);
+hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, int* nonfinite,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_band_import, dim3(grid_for(n * ldb, 256)), dim3(256), 0, st, in, ldi, n, b, Bs, ldb, nonfinite);
   return hipGetLastError();
 }
 

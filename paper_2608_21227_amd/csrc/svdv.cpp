@@ -1013,7 +1013,9 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   int rc = get_workspace(st, L.total, &ws);
   if (rc) return rc;
   double* Bs = (double*)(ws + L.Bs);
-  HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, st));
+  int* err = (int*)(ws + L.err);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
+  HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, err, st));  // sets err for a non-finite band
   ChaseArgs ca{};
   ca.Bs = Bs;
   ca.ldb = 3 * b;
@@ -1022,14 +1024,13 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   ca.W = c.sweep_width;
   ca.ngroups = (int32_t)std::max<int64_t>(1, (n - 1 + c.sweep_width - 1) / c.sweep_width);
   ca.progress = (int*)(ws + L.progress);
-  ca.err = (int*)(ws + L.err);
+  ca.err = err;
   ca.d = d;
   ca.e = e ? e : (double*)(ws + L.e);
   int grid = chase_grid(ca.ngroups, (int)b, c.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, ca.err, 0, (int64_t)1);
   HIPCHK(launch_chase(ca, grid, st));
-  // a bounded wait that gave up leaves the chase unfinished: d and e become NaN
+  // a non-finite band, or a bounded wait that gave up (the chase unfinished): d and e become NaN
   hipLaunchKernelGGL(k_nan_if_flag, dim3(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256))), dim3(256), 0,
                      st, ca.err, d, e, n);
   HIPCHK(hipGetLastError());
