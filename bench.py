@@ -139,6 +139,29 @@ def cpu_baseline(a_np: np.ndarray, n: int, dtype: str):
                       f"{_cpu_model()}; whole-run estimate {est:.0f} s"}
 
 
+def cpu_lapack(a_np: np.ndarray, n: int, dtype: str, reps: int = 2):
+    """Context beside the oracle: LAPACK's divide-and-conquer driver (numpy.linalg.svd
+    without vectors: sgesdd for float32, dgesdd for float64) on this host's cores, on the
+    same matrix, median of `reps` calls (several seconds each at n = 4096), on the same
+    4n^3/3 basis.  A comparator only."""
+    import threadpoolctl
+    info = threadpoolctl.threadpool_info()
+    blas = next((i for i in info if i.get("user_api") == "blas"), {})
+    a = np.asfortranarray(a_np)
+    np.linalg.svd(a[:256, :256], compute_uv=False)  # starts the thread pool
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        np.linalg.svd(a, compute_uv=False)
+        ts.append(time.perf_counter() - t0)
+    secs = float(np.median(ts))
+    return {"value": round((4.0 / 3.0) * n ** 3 / secs / 1e9, 3), "unit": "GFLOP/s",
+            "cores": int(blas.get("num_threads") or 0), "kind": "lapack",
+            "sample": f"numpy.linalg.svd(compute_uv=False) ({'s' if dtype == 'float32' else 'd'}gesdd, "
+                      f"{blas.get('internal_api', '?')} {blas.get('version', '?')}) on the same n={n} {dtype} matrix, "
+                      f"median of {reps}: {secs:.2f} s on {_cpu_model()}"}
+
+
 def batched_report(torch, count: int = 512, reps: int = 5):
     """512 square matrices, sizes uniform in [32, 512], known log-uniform spectra, float32:
     one batched call per repetition (the matrices grouped by their tuned configuration, each
@@ -394,6 +417,8 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a_np, n, dtype)
+        print("[bench] cpu context (LAPACK gesdd)", file=sys.stderr, flush=True)
+        out["cpu_lapack"] = cpu_lapack(a_np, n, dtype)
     if not args.no_extras:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         out["batched"] = batched_report(torch)
