@@ -140,6 +140,28 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _on(device):
+    """The tensor's device made current for the call (the library launches on the current device)."""
+    return _torch().cuda.device(device)
+
+
+def _need(t, name: str, dtype=None, dim=None, numel=None, device=None, dense=False):
+    """Argument checks done before anything reaches the library, which receives plain
+    pointers and cannot tell a short or mistyped buffer from a right one."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a tensor on a GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, not {t.dtype}")
+    if dim is not None and t.dim() != dim:
+        raise ValueError(f"{name} must be {dim}-D, not {t.dim()}-D")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the other arguments on {device}")
+    if dense and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def _as_colmajor(a):
     """(ptr, m, n, lda) of a 2-D tensor as a column-major matrix with the same singular values."""
     m, n = a.shape
@@ -168,14 +190,15 @@ def check_config(m: int, n: int, dtype: str, cfg) -> bool:
 def svd_values(a, config=None, out=None):
     """Singular values (descending) of the 2-D CUDA tensor ``a`` (float32/float64)."""
     torch = _torch()
-    if a.dim() != 2 or not a.is_cuda:
-        raise ValueError("expected a 2-D tensor on a GPU")
+    _need(a, "a", dim=2)
     dt = _dtype_code(a)
     a2, m, n, lda = _as_colmajor(a)
     k = min(m, n)
     s = out if out is not None else torch.empty(k, dtype=a.dtype, device=a.device)
-    _check(lib().svd_values_ex(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(s.data_ptr()),
-                               _stream(a.device), _cfg_ptr(config)))
+    _need(s, "out", dtype=a.dtype, numel=k, device=a.device, dense=True)
+    with _on(a.device):
+        _check(lib().svd_values_ex(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(s.data_ptr()),
+                                   _stream(a.device), _cfg_ptr(config)))
     return s
 
 
@@ -183,14 +206,13 @@ def svd_values_noalloc(a, out, config=None):
     """svd_values through the allocation-free entry point: the library works in its
     fixed device array (no device allocation); ``out`` (min(m, n) values, a's dtype)
     is supplied by the caller."""
-    if a.dim() != 2 or not a.is_cuda:
-        raise ValueError("expected a 2-D tensor on a GPU")
+    _need(a, "a", dim=2)
     dt = _dtype_code(a)
     a2, m, n, lda = _as_colmajor(a)
-    if out.numel() < min(m, n) or out.dtype != a.dtype:
-        raise ValueError("out is too small or of the wrong dtype")
-    _check(lib().svd_values_noalloc(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(out.data_ptr()),
-                                    _stream(a.device), _cfg_ptr(config)))
+    _need(out, "out", dtype=a.dtype, numel=min(m, n), device=a.device, dense=True)
+    with _on(a.device):
+        _check(lib().svd_values_noalloc(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt,
+                                        ctypes.c_void_p(out.data_ptr()), _stream(a.device), _cfg_ptr(config)))
     return out
 
 
@@ -206,7 +228,8 @@ def svd_values_batched(mats, config=None, out=None):
     dt = _dtype_code(mats[0])
     keep, ptrs, ms, ns, ldas, offs = [], [], [], [], [], []
     off = 0
-    for a in mats:
+    for i, a in enumerate(mats):
+        _need(a, f"mats[{i}]", dtype=mats[0].dtype, dim=2, device=mats[0].device)
         a2, m, n, lda = _as_colmajor(a)
         keep.append(a2)
         ptrs.append(a2.data_ptr())
@@ -216,21 +239,23 @@ def svd_values_batched(mats, config=None, out=None):
         offs.append(off)
         off += min(m, n)
     s = out if out is not None else torch.empty(max(off, 1), dtype=mats[0].dtype, device=mats[0].device)
-    if s.numel() < off or s.dtype != mats[0].dtype:
-        raise ValueError("out is too small or of the wrong dtype")
+    _need(s, "out", dtype=mats[0].dtype, numel=off, device=mats[0].device, dense=True)
     B = len(mats)
     P = (ctypes.c_void_p * B)(*ptrs)
     I64 = ctypes.c_int64 * B
-    _check(lib().svd_values_batched(ctypes.cast(P, ctypes.c_void_p), ctypes.cast(I64(*ms), ctypes.c_void_p),
-                                    ctypes.cast(I64(*ns), ctypes.c_void_p), ctypes.cast(I64(*ldas), ctypes.c_void_p),
-                                    B, dt, ctypes.c_void_p(s.data_ptr()), ctypes.cast(I64(*offs), ctypes.c_void_p),
-                                    _stream(mats[0].device), _cfg_ptr(config)))
+    with _on(mats[0].device):
+        _check(lib().svd_values_batched(ctypes.cast(P, ctypes.c_void_p), ctypes.cast(I64(*ms), ctypes.c_void_p),
+                                        ctypes.cast(I64(*ns), ctypes.c_void_p),
+                                        ctypes.cast(I64(*ldas), ctypes.c_void_p), B, dt,
+                                        ctypes.c_void_p(s.data_ptr()), ctypes.cast(I64(*offs), ctypes.c_void_p),
+                                        _stream(mats[0].device), _cfg_ptr(config)))
     return s, offs
 
 
 def stage_band(a, config=None):
     """Stage 1 only: the (k, tile+1) float64 band, row i = B(i, i..i+tile), k = min(m, n)."""
     torch = _torch()
+    _need(a, "a", dim=2)
     dt = _dtype_code(a)
     cfg = config if config is not None else default_config(*a.shape, "float32" if dt == SVDV_F32 else "float64")
     if isinstance(cfg, dict):
@@ -238,21 +263,27 @@ def stage_band(a, config=None):
     a2, m, n, lda = _as_colmajor(a)
     k = min(m, n)
     band = torch.zeros((k, cfg.tile + 1), dtype=torch.float64, device=a.device)
-    _check(lib().svdv_stage_band(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt, ctypes.c_void_p(band.data_ptr()),
-                                 cfg.tile + 1, _stream(a.device), _cfg_ptr(cfg)))
+    with _on(a.device):
+        _check(lib().svdv_stage_band(ctypes.c_void_p(a2.data_ptr()), m, n, lda, dt,
+                                     ctypes.c_void_p(band.data_ptr()), cfg.tile + 1, _stream(a.device),
+                                     _cfg_ptr(cfg)))
     return band
 
 
 def stage_bidiag(band, b: int, config=None):
     """Stage 2 only: (d, e) of the bidiagonal from a (n, >= b+1) float64 band tensor."""
     torch = _torch()
+    _need(band, "band", dtype=torch.float64, dim=2)
+    if band.shape[1] < b + 1:
+        raise ValueError(f"band has {band.shape[1]} columns, b + 1 = {b + 1} needed")
     n = band.shape[0]
     band = band.contiguous()
     d = torch.empty(n, dtype=torch.float64, device=band.device)
     e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=band.device)
-    _check(lib().svdv_stage_bidiag(ctypes.c_void_p(band.data_ptr()), n, b, band.shape[1],
-                                   ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
-                                   _stream(band.device), _cfg_ptr(config)))
+    with _on(band.device):
+        _check(lib().svdv_stage_bidiag(ctypes.c_void_p(band.data_ptr()), n, b, band.shape[1],
+                                       ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+                                       _stream(band.device), _cfg_ptr(config)))
     return d, e[: max(n - 1, 0)]
 
 
@@ -260,12 +291,18 @@ def stage_values(d, e, out_dtype=None):
     """Stage 3 only: singular values (descending) of the upper bidiagonal (d, e) (float64 tensors)."""
     torch = _torch()
     out_dtype = out_dtype or torch.float64
+    if out_dtype not in (torch.float32, torch.float64):
+        raise TypeError(f"out_dtype must be float32 or float64, not {out_dtype}")
+    _need(d, "d", dtype=torch.float64, dim=1)
     n = d.shape[0]
+    _need(e, "e", dtype=torch.float64, dim=1, numel=max(n - 1, 0), device=d.device)
     s = torch.empty(n, dtype=out_dtype, device=d.device)
-    e2 = e.contiguous() if e.numel() else d
-    _check(lib().svdv_stage_values(ctypes.c_void_p(d.contiguous().data_ptr()), ctypes.c_void_p(e2.data_ptr()), n,
-                                   SVDV_F32 if out_dtype == torch.float32 else SVDV_F64,
-                                   ctypes.c_void_p(s.data_ptr()), _stream(d.device)))
+    d2 = d.contiguous()
+    e2 = e.contiguous() if e.numel() else d2
+    with _on(d.device):
+        _check(lib().svdv_stage_values(ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(e2.data_ptr()), n,
+                                       SVDV_F32 if out_dtype == torch.float32 else SVDV_F64,
+                                       ctypes.c_void_p(s.data_ptr()), _stream(d.device)))
     return s
 
 
@@ -275,14 +312,26 @@ def apply_qt(V, T, C, side: int = 0, config=None):
     V, T, C are column-major CUDA tensors given as torch views of their transposes is NOT assumed:
     pass tensors whose .T is contiguous (i.e. Fortran order), e.g. ``x.t().contiguous().t()``."""
     dt = _dtype_code(C)
-    for x in (V, T, C):
-        if x.stride(0) != 1:
-            raise ValueError("apply_qt expects column-major (Fortran-order) tensors")
+
+    def ld(name, x):  # leading dimension of a column-major (Fortran-order) 2-D tensor
+        _need(x, name, dtype=C.dtype, dim=2, device=C.device)
+        if x.shape[1] <= 1:
+            return max(1, x.shape[0])
+        if (x.stride(0) != 1 and x.shape[0] > 1) or x.stride(1) < x.shape[0]:
+            raise ValueError(f"apply_qt expects column-major (Fortran-order) tensors; {name} is not")
+        return x.stride(1)
+
+    ldv, ldt, ldc = ld("V", V), ld("T", T), ld("C", C)
     h, w = C.shape
     k = V.shape[1]
-    _check(lib().svdv_apply_qt(ctypes.c_void_p(V.data_ptr()), V.stride(1), ctypes.c_void_p(T.data_ptr()),
-                               T.stride(1), ctypes.c_void_p(C.data_ptr()), C.stride(1), h, w, k, dt, side,
-                               _stream(C.device), _cfg_ptr(config)))
+    if V.shape[0] != (h if side == 0 else w):
+        raise ValueError(f"V has {V.shape[0]} rows, the reflector length is {h if side == 0 else w}")
+    if T.shape[0] < k or T.shape[1] < k:
+        raise ValueError(f"T is {tuple(T.shape)}, at least {k} x {k} needed")
+    with _on(C.device):
+        _check(lib().svdv_apply_qt(ctypes.c_void_p(V.data_ptr()), ldv, ctypes.c_void_p(T.data_ptr()), ldt,
+                                   ctypes.c_void_p(C.data_ptr()), ldc, h, w, k, dt, side, _stream(C.device),
+                                   _cfg_ptr(config)))
     return C
 
 
@@ -329,9 +378,20 @@ def _ptr(t):
 def mlp_forward(params, X, out=None):
     """Model outputs for the rows of X (float32 CUDA tensors; params has MLP_NPARAM entries)."""
     torch = _torch()
+    _mlp_args(params, X)
     y = out if out is not None else torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
-    _check(lib().svdv_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), _stream(X.device)))
+    _need(y, "out", dtype=torch.float32, numel=X.shape[0], device=X.device, dense=True)
+    with _on(X.device):
+        _check(lib().svdv_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), _stream(X.device)))
     return y
+
+
+def _mlp_args(params, X):
+    torch = _torch()
+    _need(params, "params", dtype=torch.float32, numel=MLP_NPARAM, dense=True)
+    _need(X, "X", dtype=torch.float32, dim=2, device=params.device, dense=True)
+    if X.shape[1] != MLP_IN:
+        raise ValueError(f"X must have {MLP_IN} feature columns, not {X.shape[1]}")
 
 
 def mlp_work(n: int, device):
@@ -341,12 +401,25 @@ def mlp_work(n: int, device):
 
 def mlp_gradient(params, X, t, grad, loss=None, work=None):
     """grad <- d/dparams of mean((model(X) - t)^2); loss (1-element tensor) receives the loss."""
-    work = work if work is not None else mlp_work(X.shape[0], X.device)
-    _check(lib().svdv_mlp_gradient(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grad),
-                                   _ptr(loss) if loss is not None else None, _ptr(work), _stream(X.device)))
+    torch = _torch()
+    _mlp_args(params, X)
+    n = X.shape[0]
+    _need(t, "t", dtype=torch.float32, numel=n, device=X.device, dense=True)
+    _need(grad, "grad", dtype=torch.float32, numel=MLP_NPARAM, device=X.device, dense=True)
+    if loss is not None:
+        _need(loss, "loss", dtype=torch.float32, numel=1, device=X.device, dense=True)
+    work = work if work is not None else mlp_work(n, X.device)
+    _need(work, "work", dtype=torch.float32, numel=int(lib().svdv_mlp_work_size(n)), device=X.device, dense=True)
+    with _on(X.device):
+        _check(lib().svdv_mlp_gradient(_ptr(params), _ptr(X), _ptr(t), n, _ptr(grad),
+                                       _ptr(loss) if loss is not None else None, _ptr(work), _stream(X.device)))
     return grad
 
 
 def mlp_adam_step(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
-    _check(lib().svdv_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
-                                    _stream(params.device)))
+    torch = _torch()
+    for name, x in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _need(x, name, dtype=torch.float32, numel=MLP_NPARAM, device=params.device, dense=True)
+    with _on(params.device):
+        _check(lib().svdv_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                                        _stream(params.device)))

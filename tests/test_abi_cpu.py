@@ -79,3 +79,19 @@ def test_reduced_precision_config_rules():
     assert not svdv.check_config(512, 512, "float64", ok)  # float32 input only
     assert not svdv.check_config(512, 512, "float32", svdv.Config(16, 1024, 1, 4, 1))  # no such precision
     assert not svdv.check_config(512, 512, "float32", svdv.Config(16, 256, 2, 4, 2))  # streaming-only configuration
+
+
+def test_binding_rejects_host_tensors_before_the_library():
+    """The binding checks its tensors before any pointer reaches the library (which
+    cannot tell a host pointer from a device one): host tensors raise at once."""
+    torch = pytest.importorskip("torch")
+    a = torch.zeros((4, 4))
+    d, e = torch.zeros(4, dtype=torch.float64), torch.zeros(3, dtype=torch.float64)
+    for call in (lambda: svdv.svd_values(a), lambda: svdv.stage_band(a),
+                 lambda: svdv.stage_bidiag(torch.zeros((4, 17), dtype=torch.float64), 16),
+                 lambda: svdv.stage_values(d, e), lambda: svdv.svd_values_batched([a]),
+                 lambda: svdv.apply_qt(a, a, a), lambda: svdv.mlp_forward(torch.zeros(svdv.MLP_NPARAM), a)):
+        with pytest.raises(ValueError, match="on a GPU"):
+            call()
+    with pytest.raises(TypeError, match="out_dtype"):
+        svdv.stage_values(d, e, out_dtype=torch.int32)

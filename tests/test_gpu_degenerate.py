@@ -167,3 +167,35 @@ def test_nonfinite_stage_inputs_give_nan():
             assert np.all(np.isnan(s))
     s = svdv.stage_values(to_dev(dv, torch), to_dev(ev, torch)).cpu().numpy()
     assert np.all(np.isfinite(s))
+
+
+# ----------------------------------------------------------------------------- binding argument checks
+def test_binding_rejects_mistyped_or_short_buffers():
+    """Buffers the library would misread (wrong dtype, too short, wrong shape) raise in
+    the binding before any launch."""
+    torch = torch_cuda()
+    svdv = _svdv()
+    f32 = lambda *s: torch.zeros(*s, dtype=torch.float32, device="cuda")
+    f64 = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")
+    banner("binding argument checks (no launch)")
+    with pytest.raises(ValueError, match="out holds"):
+        svdv.svd_values(f32(10, 8), out=f32(7))
+    with pytest.raises(TypeError, match="out must be"):
+        svdv.svd_values(f32(10, 8), out=f64(8))
+    with pytest.raises(TypeError, match="band must be"):
+        svdv.stage_bidiag(f32(40, 17), 16)
+    with pytest.raises(ValueError, match="b \\+ 1"):
+        svdv.stage_bidiag(f64(40, 12), 16)
+    with pytest.raises(TypeError, match="d must be"):
+        svdv.stage_values(f32(10), f64(9))
+    with pytest.raises(ValueError, match="e holds"):
+        svdv.stage_values(f64(10), f64(5))
+    with pytest.raises(TypeError, match="mats\\[1\\]"):
+        svdv.svd_values_batched([f32(9, 9), f64(9, 9)])
+    C = f32(30, 20).t().contiguous().t()
+    with pytest.raises(ValueError, match="reflector length"):
+        svdv.apply_qt(f32(20, 4).t().contiguous().t(), f32(4, 4).t().contiguous().t(), C, side=0)
+    with pytest.raises(ValueError, match="column-major"):
+        svdv.apply_qt(f32(30, 4), f32(4, 4).t().contiguous().t(), C, side=0)
+    with pytest.raises(ValueError, match="feature columns"):
+        svdv.mlp_forward(f32(svdv.MLP_NPARAM), f32(5, 4))
