@@ -199,3 +199,27 @@ def test_binding_rejects_mistyped_or_short_buffers():
         svdv.apply_qt(f32(30, 4), f32(4, 4).t().contiguous().t(), C, side=0)
     with pytest.raises(ValueError, match="feature columns"):
         svdv.mlp_forward(f32(svdv.MLP_NPARAM), f32(5, 4))
+
+
+# ----------------------------------------------------------------------------- extreme magnitudes
+@pytest.mark.parametrize("dtype,k_exact,k_sub", [("float32", 100, -132), ("float64", 1000, -1062)])
+def test_extreme_magnitudes(dtype, k_exact, k_sub):
+    """Staging scales the input by a power of two into [0.5, 1) before anything else
+    (reading R3), so 2^k A has exactly 2^k times the values of A while 2^k A is
+    exact (near the overflow threshold here), and an input in the subnormal range is
+    as accurate as the same input rescaled exactly into the normal range."""
+    torch = torch_cuda()
+    svdv = _svdv()
+    a = workloads.as_dtype(_rng(12).standard_normal((180, 150)), dtype)
+    banner(f"extreme magnitudes {dtype}: 2^{k_exact}, 2^{k_sub}")
+    s = svdv.svd_values(to_dev(a, torch, fortran=True)).cpu().numpy()
+    big = np.ldexp(a, k_exact)
+    assert np.all(np.isfinite(big)) and np.array_equal(np.ldexp(big, -k_exact), a)
+    s_big = svdv.svd_values(to_dev(big, torch, fortran=True)).cpu().numpy()
+    assert np.array_equal(s_big, np.ldexp(s, k_exact))
+    tiny = np.ldexp(a, k_sub)  # partly subnormal: the input itself loses low bits
+    assert np.min(np.abs(tiny[tiny != 0])) < np.finfo(a.dtype).tiny
+    s_tiny = svdv.svd_values(to_dev(tiny, torch, fortran=True)).cpu().numpy().astype(np.float64)
+    ref = np.ldexp(oracle.svd_values(np.ldexp(tiny.astype(np.float64), -k_sub)), k_sub)  # exact rescaling
+    nw = np.max(np.abs(s_tiny - ref)) / ref[0]
+    assert nw <= (1e-5 if dtype == "float32" else 1e-12), f"normwise {nw:.3e}"
