@@ -200,16 +200,27 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
   } else {
     constexpr int EPT = TILE / 16;  // elements of one 64 x TILE block per thread
     constexpr int CQB = C::CQB;
+    // the next group of blocks is requested before this one goes through LDS, so
+    // the global loads of consecutive groups overlap instead of queueing
+    TC tmp[CQB][EPT], nxt[CQB][EPT];
+#pragma unroll
+    for (int ib = 0; ib < CQB; ++ib)
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int t = threadIdx.x + k * 1024;
+        tmp[ib][k] = fetch(ib * 64 + t / TILE, t % TILE);
+      }
 #pragma unroll
     for (int i0 = 0; i0 < RPT; i0 += CQB) {
-      TC tmp[CQB][EPT];
+      if (i0 + CQB < RPT) {
 #pragma unroll
-      for (int ib = 0; ib < CQB; ++ib)
+        for (int ib = 0; ib < CQB; ++ib)
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const int t = threadIdx.x + k * 1024;
-          tmp[ib][k] = fetch((i0 + ib) * 64 + t / TILE, t % TILE);
-        }
+          for (int k = 0; k < EPT; ++k) {
+            const int t = threadIdx.x + k * 1024;
+            nxt[ib][k] = fetch((i0 + CQB + ib) * 64 + t / TILE, t % TILE);
+          }
+      }
 #pragma unroll
       for (int ib = 0; ib < CQB; ++ib)
 #pragma unroll
@@ -223,6 +234,12 @@ __device__ __forceinline__ void chunk_qr_body(const ChunkQRArgs<T>& a, const int
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) x[i0 + ib][cc] = stage[(ib * 64 + l) * (TILE + 1) + w * CPT + cc];
       __syncthreads();
+      if (i0 + CQB < RPT) {
+#pragma unroll
+        for (int ib = 0; ib < CQB; ++ib)
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) tmp[ib][k] = nxt[ib][k];
+      }
     }
   }
 
