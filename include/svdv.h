@@ -172,8 +172,9 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
  * (float64, n and n-1 entries), written descending to S in out_dtype.  Each
  * value is located by Sturm-count multisection in float64 to an absolute
  * width of 4u (max|d| + max|e|) for SVDV_F64 output and 2^-32 (max|d| + max|e|)
- * for SVDV_F32 output, then rounded to out_dtype.  If d or e holds a NaN or an
- * infinity, every value is NaN.
+ * for SVDV_F32 output, then rounded to out_dtype.  Any finite magnitude is
+ * accepted (d and e are scaled by a power of two internally, exactly).  If d or
+ * e holds a NaN or an infinity, every value is NaN.
  */
 int svdv_stage_values(const double* d, const double* e, int64_t n, int32_t out_dtype, void* S, void* stream);
 

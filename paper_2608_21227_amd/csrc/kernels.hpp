@@ -191,10 +191,10 @@ hipError_t launch_chase_batched(const ChaseArgs& L, int grid, int count, int64_t
 // Work array of an n x n bidiagonal: d_i^2 [n], e_i^2 [n], bound, pivmin, then
 // the int32 counts of the shared grid (bisect_grid_points(n) of them).
 __host__ __device__ inline int64_t bisect_grid_points(int64_t n) { return 16 * n; }
-__host__ __device__ inline int64_t bisect_work_doubles(int64_t n) { return 2 * n + 2 + (bisect_grid_points(n) + 1) / 2; }
-__host__ __device__ inline int* bisect_grid_counts(double* work, int64_t n) { return (int*)(work + 2 * n + 2); }
+__host__ __device__ inline int64_t bisect_work_doubles(int64_t n) { return 2 * n + 3 + (bisect_grid_points(n) + 1) / 2; }
+__host__ __device__ inline int* bisect_grid_counts(double* work, int64_t n) { return (int*)(work + 2 * n + 3); }
 __host__ __device__ inline const int* bisect_grid_counts(const double* work, int64_t n) {
-  return (const int*)(work + 2 * n + 2);
+  return (const int*)(work + 2 * n + 3);
 }
 // lanes_per_value: 8, 16, 32 or 64, or 0 to choose from n.
 // fail_flag (optional): when it holds a nonzero value (a bounded wait of the chase

@@ -18,42 +18,56 @@
 
 namespace svdv {
 
-// work layout: dd[n], ee[n], then [2*n] = bound, [2*n+1] = pivmin
+// work layout: dd[n], ee[n] (the squares of d and e scaled by 2^-k), then
+// [2*n] = bound, [2*n+1] = pivmin, [2*n+2] = k, then the grid counts.
+// d and e are scaled by the power of two 2^-k that brings max(|d|, |e|) into
+// [0.5, 1) (exact), so that the squares and the pivot bounds below hold for any
+// finite input; the output stage scales the values back by 2^k.
 __device__ __forceinline__ void bisect_prep_body(const double* __restrict__ d, const double* __restrict__ e, int64_t n,
                                                  double* work) {
-  __shared__ double smax[4][256];
-  double md = 0.0, me = 0.0, me2 = 0.0, bad = 0.0;
+  __shared__ double smax[3][256];
+  __shared__ int s_k;
+  double md = 0.0, me = 0.0, bad = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     const double di = d[i];
     const double ei = i + 1 < n ? e[i] : 0.0;
-    work[i] = di * di;
-    work[n + i] = ei * ei;
     md = fmax(md, fabs(di));
     me = fmax(me, fabs(ei));
-    me2 = fmax(me2, ei * ei);
     if (!isfinite(di) || !isfinite(ei)) bad = 1.0;
   }
   smax[0][threadIdx.x] = md;
   smax[1][threadIdx.x] = me;
-  smax[2][threadIdx.x] = me2;
-  smax[3][threadIdx.x] = bad;
+  smax[2][threadIdx.x] = bad;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int k = 0; k < 4; ++k) smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
+      for (int k = 0; k < 3; ++k) smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
     __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mx = fmax(smax[0][0], smax[1][0]);
+    s_k = (smax[2][0] == 0.0 && mx > 0.0) ? ilogb(mx) + 1 : 0;
+  }
+  __syncthreads();
+  const int k = s_k;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double di = ldexp(d[i], -k);
+    const double ei = i + 1 < n ? ldexp(e[i], -k) : 0.0;
+    work[i] = di * di;
+    work[n + i] = ei * ei;
   }
   if (threadIdx.x == 0) {
     // a NaN or an infinity in d or e: the bound is NaN, which every search stops
     // on at once and the output stage writes as NaN
-    const double bound =
-        smax[3][0] != 0.0 ? __builtin_nan("") : (smax[0][0] + smax[1][0]) * (1.0 + 1e-14) + DBL_MIN;
+    const double bound = smax[2][0] != 0.0 ? __builtin_nan("")
+                                           : ldexp(smax[0][0] + smax[1][0], -k) * (1.0 + 1e-14) + DBL_MIN;
     work[2 * n] = bound;
     // pivmin = 2^p >= bound^2 2^-896.  With G = bound^2 >= d_i^2, e_i^2, x^2 every
     // |s_i| <= 2 G^2 / pivmin + G <= 2^897 G and every |D+_i| >= pivmin, so all
-    // pivots and their reciprocals stay normal (as long as G < 2^120).  Pivots this
-    // small are a perturbation far below the rounding error of the reduction.
+    // pivots and their reciprocals stay normal (G <= 4 after the scaling).  Pivots
+    // this small are a perturbation far below the rounding error of the reduction.
     work[2 * n + 1] = isfinite(bound) ? ldexp(1.0, max(2 * ilogb(bound) + 2 - 896, -1000)) : 1.0;
+    work[2 * n + 2] = (double)k;
   }
 }
 
@@ -202,8 +216,11 @@ __device__ __forceinline__ void bisect_team(const double* __restrict__ work, int
   if (active && j == 0) {
     const int e = *exp_in;
     // NaN for an input with a NaN or an infinity (marked in the exponent at
-    // staging, or in the bound by the preparation of d and e)
-    S[n - 1 - k] = (e == kExpNonFinite || !isfinite(bound)) ? (T)__builtin_nan("") : (T)ldexp(0.5 * (lo + hi), e);
+    // staging, or in the bound by the preparation of d and e); otherwise the
+    // value scaled back by the preparation's 2^k and the staging's 2^e
+    S[n - 1 - k] = (e == kExpNonFinite || !isfinite(bound))
+                       ? (T)__builtin_nan("")
+                       : (T)ldexp(0.5 * (lo + hi), e + (int)work[2 * n + 2]);
   }
 }
 

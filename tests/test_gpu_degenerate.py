@@ -223,3 +223,20 @@ def test_extreme_magnitudes(dtype, k_exact, k_sub):
     ref = np.ldexp(oracle.svd_values(np.ldexp(tiny.astype(np.float64), -k_sub)), k_sub)  # exact rescaling
     nw = np.max(np.abs(s_tiny - ref)) / ref[0]
     assert nw <= (1e-5 if dtype == "float32" else 1e-12), f"normwise {nw:.3e}"
+
+
+@pytest.mark.parametrize("k", [200, 900, -600, -1000])
+def test_stage_values_any_magnitude(k):
+    """Stage 3 alone takes (d, e) as given: values of 2^k (d, e) are exactly 2^k times
+    those of (d, e) wherever 2^k (d, e) is representable without rounding."""
+    torch = torch_cuda()
+    svdv = _svdv()
+    r = _rng(13)
+    d, e = r.standard_normal(300), r.standard_normal(299)
+    banner(f"stage_values at scale 2^{k}")
+    want = svdv.stage_values(to_dev(d, torch), to_dev(e, torch)).cpu().numpy()
+    ds, es = np.ldexp(d, k), np.ldexp(e, k)
+    assert np.array_equal(np.ldexp(ds, -k), d) and np.array_equal(np.ldexp(es, -k), e)
+    got = svdv.stage_values(to_dev(ds, torch), to_dev(es, torch)).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert np.array_equal(got, np.ldexp(want, k))
