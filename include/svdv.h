@@ -160,6 +160,8 @@ int svdv_stage_band(const void* A, int64_t m, int64_t n, int64_t lda, int32_t dt
  * d[0..n-1] (diagonal) and e[0..n-2] (superdiagonal), float64.  Signs of d, e
  * are not normalised.  cfg->sweep_width selects the schedule; the result is
  * bitwise identical for every sweep_width.  b must be one of the tile sizes.
+ * Any finite magnitude is accepted (the band is scaled by a power of two
+ * internally, exactly, and d and e scaled back).
  * If the band holds a NaN or an infinity, or a bounded wait between the
  * chase's workgroups gives up (it never does in a correct launch), every entry
  * of d and e is NaN after the stream completes.

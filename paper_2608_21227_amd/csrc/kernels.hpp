@@ -120,7 +120,7 @@ struct BatchMat {
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n);
 __global__ void k_fill_i32(int* p, int v, int64_t n);
 __global__ void k_fill_f64(double* p, double v, int64_t n);
-__global__ void k_nan_if_flag(const int* flag, double* d, double* e, int64_t n);
+__global__ void k_finish_de(const int* flag, const int* exp, double* d, double* e, int64_t n);
 
 template <typename T>
 hipError_t launch_stage_in(const T* A, int64_t m, int64_t n, int64_t lda, int transpose, T* W, int64_t ldw,
@@ -155,6 +155,10 @@ hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double
                                hipStream_t st);
 hipError_t launch_band_import(const double* in, int64_t ldi, int64_t n, int b, double* Bs, int64_t ldb, int* nonfinite,
                               hipStream_t st);
+// max |Bs| over n rows of ldb entries, then Bs scaled in place by the power of two
+// 2^-e that brings it into [0.5, 1); *exp_out receives e
+hipError_t launch_band_scale(double* Bs, int64_t ldb, int64_t n, unsigned long long* amax, int* exp_out,
+                             hipStream_t st);
 
 // Stage 2.
 struct ChaseArgs {

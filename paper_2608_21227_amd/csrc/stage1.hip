@@ -49,14 +49,16 @@ __global__ void k_fill_i32(int* p, int v, int64_t n) {
 __global__ void k_fill_f64(double* p, double v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
-// d[0 .. n) and e[0 .. n-1) become NaN when *flag is nonzero (the chase that was to
-// write them gave up a bounded wait), so no caller reads them as valid.
-__global__ void k_nan_if_flag(const int* flag, double* d, double* e, int64_t n) {
-  if (*flag == 0) return;
+// d[0 .. n) and e[0 .. n-1) of stage 2 run alone: NaN when *flag is nonzero (a
+// non-finite band, or a chase that gave up a bounded wait), so no caller reads them
+// as valid; otherwise scaled back by 2^(*exp), the power of two the band was scaled by.
+__global__ void k_finish_de(const int* flag, const int* exp, double* d, double* e, int64_t n) {
+  const bool bad = *flag != 0;
+  const int k = bad ? 0 : *exp;
   const double q = __builtin_nan("");
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    d[i] = q;
-    if (i + 1 < n) e[i] = q;
+    d[i] = bad ? q : ldexp(d[i], k);
+    if (i + 1 < n) e[i] = bad ? q : ldexp(e[i], k);
   }
 }
 
@@ -681,6 +683,28 @@ hipError_t launch_band_extract(const T* W, int64_t ldw, int64_t n, int b, double
                                hipStream_t st) {
   hipLaunchKernelGGL(k_band_extract<T>, dim3(grid_for(n * (b + 1), 256)), dim3(256), 0, st, W, ldw, n, b, out, ldo,
                      exp_in);
+  return hipGetLastError();
+}
+
+// In-place exact scaling of the chase storage by 2^-e, e = scale_exponent(*amax), so
+// that the chase's norms neither overflow nor underflow for any finite band; *exp_out
+// receives e (the marker of a non-finite input leaves the data as it is).
+__global__ void k_scale_inplace(double* p, int64_t count, const unsigned long long* amax, int* exp_out) {
+  const int e = scale_exponent(*amax);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double mx = __longlong_as_double((long long)*amax);
+    *exp_out = isfinite(mx) ? e : kExpNonFinite;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = ldexp(p[i], -e);
+}
+
+hipError_t launch_band_scale(double* Bs, int64_t ldb, int64_t n, unsigned long long* amax, int* exp_out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, amax, 0ull, (int64_t)1);
+  hipLaunchKernelGGL(k_absmax<double>, dim3(std::min(grid_for(n * ldb, 256), 1024)), dim3(256), 0, st, Bs, ldb, n,
+                     ldb, amax);
+  hipLaunchKernelGGL(k_scale_inplace, dim3(grid_for(n * ldb, 256)), dim3(256), 0, st, Bs, n * ldb, amax, exp_out);
   return hipGetLastError();
 }
 

@@ -1016,6 +1016,10 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   int* err = (int*)(ws + L.err);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, err, 0, (int64_t)1);
   HIPCHK(launch_band_import(band, ldband, n, (int)b, Bs, 3 * b, err, st));  // sets err for a non-finite band
+  // the band as given may lie anywhere in the float64 range: scale it by a power of
+  // two into [0.5, 1) (exact) and scale d and e back at the end
+  int* expo = (int*)(ws + L.exp);
+  HIPCHK(launch_band_scale(Bs, 3 * b, n, (unsigned long long*)(ws + L.amax), expo, st));
   ChaseArgs ca{};
   ca.Bs = Bs;
   ca.ldb = 3 * b;
@@ -1030,9 +1034,10 @@ int svdv_stage_bidiag(const double* band, int64_t n, int64_t b, int64_t ldband, 
   int grid = chase_grid(ca.ngroups, (int)b, c.sweep_width);
   if (grid < 1) return fail(SVDV_ERR_UNSUPPORTED, "bulge-chase kernel cannot be resident with this configuration");
   HIPCHK(launch_chase(ca, grid, st));
-  // a non-finite band, or a bounded wait that gave up (the chase unfinished): d and e become NaN
-  hipLaunchKernelGGL(k_nan_if_flag, dim3(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256))), dim3(256), 0,
-                     st, ca.err, d, e, n);
+  // a non-finite band, or a bounded wait that gave up (the chase unfinished): d and e
+  // become NaN; otherwise they are scaled back
+  hipLaunchKernelGGL(k_finish_de, dim3(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256))), dim3(256), 0,
+                     st, ca.err, expo, d, ca.e, n);
   HIPCHK(hipGetLastError());
   return SVDV_OK;
 }

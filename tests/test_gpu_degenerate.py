@@ -240,3 +240,23 @@ def test_stage_values_any_magnitude(k):
     got = svdv.stage_values(to_dev(ds, torch), to_dev(es, torch)).cpu().numpy()
     assert np.all(np.isfinite(got))
     assert np.array_equal(got, np.ldexp(want, k))
+
+
+@pytest.mark.parametrize("k", [600, 900, -600, -900])
+def test_stage_bidiag_any_magnitude(k):
+    """Stage 2 alone takes the band as given: the bidiagonal of 2^k B is exactly 2^k
+    times that of B (the band is scaled into range internally by a power of two)."""
+    torch = torch_cuda()
+    svdv = _svdv()
+    r = _rng(14)
+    n, b = 200, 16
+    band = r.standard_normal((n, b + 1))
+    for dd in range(b + 1):
+        band[n - dd:, dd] = 0.0
+    banner(f"stage_bidiag at scale 2^{k}")
+    d0, e0 = (x.cpu().numpy() for x in svdv.stage_bidiag(to_dev(band, torch), b))
+    scaled = np.ldexp(band, k)
+    assert np.array_equal(np.ldexp(scaled, -k), band)
+    d1, e1 = (x.cpu().numpy() for x in svdv.stage_bidiag(to_dev(scaled, torch), b))
+    assert np.all(np.isfinite(d1)) and np.all(np.isfinite(e1))
+    assert np.array_equal(d1, np.ldexp(d0, k)) and np.array_equal(e1, np.ldexp(e0, k))
