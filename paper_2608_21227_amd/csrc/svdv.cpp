@@ -279,6 +279,28 @@ struct Workspace {
 std::mutex g_mu;
 std::map<std::pair<int, void*>, Workspace> g_ws;
 
+// A second stream per (device, caller stream) for the upper levels of a TSQR tree,
+// which run beside the trailing update of the level below (see run_panel_step),
+// and the events that fork it from and join it to the caller's stream.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[8] = {};
+};
+std::map<std::pair<int, void*>, SideStream> g_side;
+
+int get_side(void* stream, SideStream** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  SideStream& ss = g_side[{dev, stream}];
+  if (!ss.s) {
+    HIPCHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));  // default priority
+    for (auto& e : ss.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  *out = &ss;
+  return SVDV_OK;
+}
+
 int get_workspace(void* stream, size_t bytes, char** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -341,12 +363,27 @@ Layout make_layout(int64_t M, int64_t N, int es, int tile, int hmax, int sweep_w
 // stage 1 driver
 // ----------------------------------------------------------------------------
 
+// One panel step: the TSQR levels of the panel, then the trailing update level by
+// level.  The update of level 1 (the chunks' own reflectors, Q_1^T C) does not read
+// what the levels above it compute: they factor the stacked R factors in the panel's
+// columns and write their own V and T, while that update reads level 1's V and T and
+// writes the trailing columns.  With a side stream, levels 2.. are factored there,
+// forked after level 1's factorisation, so they run beside level 1's update; the
+// update of level l waits for level l's factorisation.  Same kernels, same
+// arithmetic, in either order.
 template <typename T>
 int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t ncols, const svdv_config& cfg,
-                   T* vws, T* tws, hipStream_t st) {
+                   T* vws, T* tws, hipStream_t st, const SideStream* side) {
   const int hmax = chunk_qr_hmax<T>(cfg.tile);
   auto levels = plan_panel(r0, h, bw, cfg.tile, hmax);
-  for (auto& lv : levels) {
+  const bool fork = side != nullptr && levels.size() > 1 && levels.size() <= 8;
+  for (size_t li = 0; li < levels.size(); ++li) {
+    const auto& lv = levels[li];
+    const hipStream_t sp = fork && li > 0 ? side->s : st;
+    if (fork && li == 1) {
+      HIPCHK(hipEventRecord(side->ev[0], st));
+      HIPCHK(hipStreamWaitEvent(side->s, side->ev[0], 0));
+    }
     ChunkQRArgs<T> a;
     a.M = V;
     a.pc = pc;
@@ -359,13 +396,16 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
     a.ldv = lv.ldv;
     a.Tm = tws + lv.toff;
     a.hp = cfg.update_precision != 0 ? 1 : 0;
-    g_timing.kbegin(1, st);
-    HIPCHK(launch_chunk_qr<T>(cfg.tile, a, st));
+    g_timing.kbegin(1, sp);
+    HIPCHK(launch_chunk_qr<T>(cfg.tile, a, sp));
     // Householder QR of P chunks of (chunk rows x bw): 2 r bw^2 flops, panel read and written once
-    g_timing.kend(1, st, 2.0 * (double)lv.h * bw * bw, 2.0 * sizeof(T) * (double)lv.h * bw);
+    g_timing.kend(1, sp, 2.0 * (double)lv.h * bw * bw, 2.0 * sizeof(T) * (double)lv.h * bw);
+    if (fork && li > 0) HIPCHK(hipEventRecord(side->ev[li], side->s));
   }
   if (pc + bw < ncols) {
-    for (auto& lv : levels) {
+    for (size_t li = 0; li < levels.size(); ++li) {
+      const auto& lv = levels[li];
+      if (fork && li > 0) HIPCHK(hipStreamWaitEvent(st, side->ev[li], 0));
       LarfbArgs<T> a;
       a.M = V;
       a.rm = lv.rm;
@@ -388,25 +428,28 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
       const double w = (double)(a.col1 - a.col0);
       g_timing.kend(0, st, 4.0 * (double)lv.h * w * a.k, sizeof(T) * ((double)lv.h * w * 2.0 + (double)lv.h * a.k));
     }
+  } else if (fork) {
+    HIPCHK(hipStreamWaitEvent(st, side->ev[levels.size() - 1], 0));  // the last panel: join before the band is read
   }
   return SVDV_OK;
 }
 
 template <typename T>
-int run_stage1(T* W, int64_t ldw, int64_t M, int64_t N, const svdv_config& cfg, T* vws, T* tws, hipStream_t st) {
+int run_stage1(T* W, int64_t ldw, int64_t M, int64_t N, const svdv_config& cfg, T* vws, T* tws, hipStream_t st,
+               const SideStream* side) {
   const int b = cfg.tile;
   const View<T> colv{W, 1, ldw};
   const View<T> rowv{W, ldw, 1};
   for (int64_t k0 = 0; k0 < N; k0 += b) {
     const int bw = (int)std::min<int64_t>(b, N - k0);
     // QR sweep: tile column, rows k0..M-1, update columns k0+bw..N-1
-    int rc = run_panel_step<T>(colv, k0, k0, M - k0, bw, N, cfg, vws, tws, st);
+    int rc = run_panel_step<T>(colv, k0, k0, M - k0, bw, N, cfg, vws, tws, st, side);
     if (rc) return rc;
     // LQ sweep: tile row k0..k0+b-1, columns k0+b..N-1 (QR of the transposed view),
     // update rows k0+b..M-1 (view columns)
     const int64_t c1 = k0 + b;
     if (c1 < N) {
-      rc = run_panel_step<T>(rowv, c1, k0, N - c1, b, M, cfg, vws, tws, st);
+      rc = run_panel_step<T>(rowv, c1, k0, N - c1, b, M, cfg, vws, tws, st, side);
       if (rc) return rc;
     }
   }
@@ -460,11 +503,17 @@ int svd_values_t(const T* A, int64_t m, int64_t n, int64_t lda, T* S, hipStream_
   double* e = e_out ? e_out : (double*)(ws + L.e);
   double* work = (double*)(ws + L.work);
 
+  // the allocation-free path (ext_ws) creates nothing: its panel levels stay on one stream
+  SideStream* side = nullptr;
+  if (!ext_ws) {
+    rc = get_side(st, &side);
+    if (rc) return rc;
+  }
   g_timing.begin_call();
   g_timing.mark(0, st);
   HIPCHK(launch_stage_in<T>(A, m, n, lda, transpose, W, ldw, amax, expo, st));
   g_timing.mark(1, st);
-  rc = run_stage1<T>(W, ldw, M, N, cfg, vws, tws, st);
+  rc = run_stage1<T>(W, ldw, M, N, cfg, vws, tws, st, side);
   if (rc) return rc;
   g_timing.mark(2, st);
   if (band_out) {
@@ -1364,6 +1413,13 @@ int svdv_release(void) {
     kv.second.release();
   }
   g_batch.clear();
+  for (auto& kv : g_side) {
+    hipSetDevice(kv.first.first);
+    hipStreamSynchronize(kv.second.s);
+    for (auto& e : kv.second.ev) hipEventDestroy(e);
+    hipStreamDestroy(kv.second.s);
+  }
+  g_side.clear();
   return SVDV_OK;
 }
 
