@@ -376,7 +376,9 @@ int run_panel_step(View<T> V, int64_t r0, int64_t pc, int64_t h, int bw, int64_t
                    T* vws, T* tws, hipStream_t st, const SideStream* side) {
   const int hmax = chunk_qr_hmax<T>(cfg.tile);
   auto levels = plan_panel(r0, h, bw, cfg.tile, hmax);
-  const bool fork = side != nullptr && levels.size() > 1 && levels.size() <= 8;
+  // per-kernel timing (svdv_timing(2)) keeps one stream, so that each launch's
+  // events bracket that kernel alone and not its wait for a CU beside the update
+  const bool fork = side != nullptr && !g_timing.kernels && levels.size() > 1 && levels.size() <= 8;
   for (size_t li = 0; li < levels.size(); ++li) {
     const auto& lv = levels[li];
     const hipStream_t sp = fork && li > 0 ? side->s : st;
