@@ -80,8 +80,20 @@ __global__ void k_bisect_prep_b(const BatchMat<T>* __restrict__ tab) {
   bisect_prep_body(t.d, t.e, t.N, t.work);
 }
 
-// Sturm count of one shift x: the number of negative pivots (divisions by
-// nr_div: the choice of pivmin keeps every pivot and its reciprocal normal).  d_i^2 and e_i^2 are
+// One step of the recurrence, s' = e^2 s / D+ - x^2, as fma(e^2 s, r, -x^2) with
+// r = 1/D+ from the hardware reciprocal refined once by Newton's step: e^2 s is
+// formed beside the reciprocal, so the dependent chain per step is the pivot, the
+// reciprocal, its refinement and one fma.  Each operation has a relative error of
+// a few units in the last place, which keeps the count's backward stability.
+__device__ __forceinline__ double sturm_step(double s, double dp, double e2, double t) {
+  const double es = e2 * s;
+  double r = __builtin_amdgcn_rcp(dp);
+  r = fma(r, fma(-dp, r, 1.0), r);
+  return fma(es, r, -t);
+}
+
+// Sturm count of one shift x: the number of negative pivots (the choice of
+// pivmin keeps every pivot and its reciprocal normal).  d_i^2 and e_i^2 are
 // fetched 8 steps at a time (wave-uniform addresses, so scalar loads that are in
 // flight while the previous 8 steps run).  pivmin is a power of two, so
 // |D+| < pivmin is decided exactly on the high 32 bits of D+; the sign bit of
@@ -110,9 +122,9 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ dd, const 
       ev[u] = ee[i + u];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s = fma(ev[u], nr_div(s, pivot(dv[u])), -t);
+    for (int u = 0; u < 8; ++u) s = sturm_step(s, pivot(dv[u]), ev[u], t);
   }
-  for (; i + 1 < n; ++i) s = fma(ee[i], nr_div(s, pivot(dd[i])), -t);
+  for (; i + 1 < n; ++i) s = sturm_step(s, pivot(dd[i]), ee[i], t);
   pivot(dd[n - 1]);  // last pivot (no e beyond it)
   return cnt;
 }
